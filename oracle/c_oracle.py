@@ -1,0 +1,79 @@
+"""ctypes wrapper of the C row-slice oracle (hv_oracle.c).
+
+Test infrastructure only.  rows_hv(desc, terms, rows, v, states=None)
+evaluates u[s] = sum_t <s|H|t> v[t] for the given row configurations.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from synth.lattices import SPIN_BOND, SPIN_FIELD, HOP, DENS, NUM, HUBBARD_U
+from .build import LIB, build
+
+_KIND = {SPIN_BOND: 0, SPIN_FIELD: 1, HOP: 2, DENS: 3, NUM: 4, HUBBARD_U: 5}
+
+
+class _OTerm(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i", C.c_int32), ("j", C.c_int32), ("reserved", C.c_int32),
+                ("c", C.c_double * 9)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        for name in ("oracle_hv_rows", "oracle_hv_rows_c64"):
+            fn = getattr(L, name)
+            fn.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                           C.c_int, C.c_void_p]
+            fn.restype = C.c_int
+        L.oracle_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _terms(terms):
+    arr = (_OTerm * max(1, len(terms)))()
+    for n, t in enumerate(terms):
+        arr[n].kind = _KIND[t.kind]
+        arr[n].i = t.i
+        arr[n].j = t.j
+        for k, x in enumerate(t.c):
+            arr[n].c[k] = x
+    return arr
+
+
+def threads() -> int:
+    return lib().oracle_max_threads()
+
+
+def rows_hv(terms, rows: np.ndarray, v: np.ndarray, states: np.ndarray | None = None) -> np.ndarray:
+    """u for the row configurations `rows`; v is (dim,) or (dim, nvec), complex128 or complex64."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    nvec = 1 if v.ndim == 1 else v.shape[1]
+    if nvec > 64:
+        raise ValueError("nvec <= 64")
+    dim = v.shape[0]
+    if v.dtype == np.complex64:
+        fn = lib().oracle_hv_rows_c64
+    else:
+        v = v.astype(np.complex128, copy=False)
+        fn = lib().oracle_hv_rows
+    v = np.ascontiguousarray(v)
+    u = np.zeros((len(rows), nvec), dtype=np.complex128)
+    st = None if states is None else np.ascontiguousarray(states, dtype=np.uint64)
+    arr = _terms(terms)
+    rc = fn(arr, len(terms), None if st is None else st.ctypes.data, dim, rows.ctypes.data, len(rows),
+            v.ctypes.data, nvec, u.ctypes.data)
+    if rc != 0:
+        raise ValueError("a term leaves the basis")
+    return u if v.ndim == 2 else u[:, 0]

@@ -273,3 +273,26 @@ def sector_preserving(desc, terms) -> bool:
     except ValueError:
         return False
     return True
+
+
+def row_elements_sampled(desc, terms, row_states: np.ndarray, rank_fn):
+    """Elements of selected rows without a full basis list.
+
+    By Hermiticity of each term, <s|T|t> = conj(<t|T|s>): each term is
+    applied to |s> and the reached states t give the elements of row s.
+    rank_fn maps configurations to indices.  Returns a list (one dict per
+    row) of {(col, term_id): value}, diagonal parts summed under term -1.
+    """
+    st = np.asarray(row_states, dtype=np.uint64)
+    own = rank_fn(st)
+    out = [dict() for _ in range(len(st))]
+    for tid, term in enumerate(terms):
+        for coef, tgt in term_action(term, st, desc.particle):
+            nz = np.nonzero(coef != 0)[0]
+            if nz.size == 0:
+                continue
+            cols = rank_fn(tgt[nz])
+            for k, c, val in zip(nz, cols, np.conj(coef[nz])):
+                key = (int(c), -1) if int(c) == int(own[k]) else (int(c), tid)
+                out[k][key] = out[k].get(key, 0.0) + val
+    return [{k: v for k, v in d.items() if v != 0} for d in out]

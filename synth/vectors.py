@@ -42,3 +42,22 @@ def uniform_vectors(dim: int, seeds, complex_: bool, dtype=None) -> np.ndarray:
     if dtype is not None:
         out = out.astype(dtype)
     return out
+
+
+def device_uniform(dim: int, nvec: int, seed: int, complex_: bool, dtype, device="cuda"):
+    """Seeded uniform [-1, 1) vectors drawn with torch's generator on the device.
+
+    Shape (dim, nvec) (or (dim,) for nvec = 0), values rounded to `dtype`;
+    used for full-size inputs where a host draw would dominate set-up time.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    shape = (dim, max(nvec, 1))
+    real_dt = torch.float32 if dtype in (torch.float32, torch.complex64) else torch.float64
+    if complex_:
+        x = torch.rand(shape + (2,), generator=g, device=device, dtype=real_dt) * 2 - 1
+        out = torch.view_as_complex(x.contiguous()).to(dtype)
+    else:
+        out = (torch.rand(shape, generator=g, device=device, dtype=real_dt) * 2 - 1).to(dtype)
+    return out.reshape(dim) if nvec == 0 else out.contiguous()

@@ -431,3 +431,52 @@ def test_tpq_matches_spectral_closed_form():
     assert abs(u[0] - np.trace(H).real / H.shape[0] / ns) < 5 / np.sqrt(H.shape[0])
     beta = osv.tpq_beta(u, ns, 1.5)
     assert beta[0] == 0 and np.all(np.diff(beta) > 0)
+
+
+def test_row_elements_sampled_matches_push():
+    """Row-wise elements from applying terms to |s> equal the column-wise push (Hermiticity)."""
+    desc = BasisDesc("fermion", 4, "nupndn", n_up=2, n_dn=2)
+    terms = L.random_fermion_terms(4, 9, 41, conserve_spin=True, real=False, n_dens=2, with_mu=True)
+    st = ob.states(desc)
+    rows = np.array([0, 5, 17, len(st) - 1])
+    push = oh.row_elements(desc, terms, rows, st)
+    pull = oh.row_elements_sampled(desc, terms, st[rows], lambda t: ob.rank(st, t))
+    for k, r in enumerate(rows):
+        assert push[int(r)].keys() == pull[k].keys()
+        for key in push[int(r)]:
+            assert abs(push[int(r)][key] - pull[k][key]) < 1e-15
+
+
+# ------------------------------------------------------------ C row oracle
+
+@pytest.mark.parametrize("seed,real", [(51, False), (52, True)])
+def test_c_oracle_spin_matches_kron(seed, real):
+    """C oracle rows against the Kronecker-product matrix (independent construction)."""
+    from oracle import c_oracle
+    n = 7
+    terms = L.random_spin_terms(n, 11, seed, conserve_sz=False, fields=True, real=real)
+    Hk = _kron_spin_h(n, terms)
+    v = uniform_vectors(2 ** n, [1, 2, 3], True)
+    rows = np.arange(2 ** n, dtype=np.uint64)
+    u = c_oracle.rows_hv(terms, rows, v)
+    assert np.allclose(u, Hk @ v, atol=1e-13, rtol=0)
+
+
+def test_c_oracle_fermion_matches_jordan_wigner():
+    from oracle import c_oracle
+    ns = 3
+    terms = L.random_fermion_terms(ns, 9, 53, conserve_spin=False, real=False, n_dens=3, with_mu=True)
+    Hk = _kron_fermion_h(ns, terms)
+    v = uniform_vectors(4 ** ns, [4, 5], True)
+    u = c_oracle.rows_hv(terms, np.arange(4 ** ns, dtype=np.uint64), v)
+    assert np.allclose(u, Hk @ v, atol=1e-13, rtol=0)
+
+
+def test_c_oracle_sector_rows_match_python_oracle():
+    from oracle import c_oracle
+    desc = BasisDesc("fermion", 5, "nupndn", n_up=2, n_dn=2)
+    terms = L.random_fermion_terms(5, 12, 54, conserve_spin=True, real=False, n_dens=2)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), [6], True)[:, 0]
+    u = c_oracle.rows_hv(terms, st, v, states=st)
+    assert np.allclose(u, oh.apply_h(desc, terms, v, st), atol=1e-13, rtol=0)
