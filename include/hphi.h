@@ -1,0 +1,267 @@
+/*
+ * hphi.h -- C ABI of the MI355X matrix-free H.v / Lanczos / TPQ library.
+ *
+ * Implements the hot path of Kawamura et al., "Quantum Lattice Model
+ * Solver HPhi" (arXiv:1703.03637) on one AMD Instinct MI355X (gfx950):
+ *   - the bit-string Hilbert space and its canonical (fixed Sz or fixed
+ *     particle number) restriction with two-dimensional (split-table)
+ *     reverse lookup                                     (Sec. 3.1)
+ *   - the on-the-fly Hamiltonian-vector product: diagonal terms, XOR
+ *     exchange / hopping after a bit test, fermion sign from the parity
+ *     of a masked bit count                              (Sec. 3.3)
+ *   - the Lanczos ground-state iteration with the second pass for the
+ *     eigenvector and the energy/variance check (Sec. 3.4, App. A.3)
+ *   - the microcanonical TPQ step                         (Sec. 3.5)
+ *
+ * Conventions (bind every entry point):
+ *   * Site i of a spin-1/2 system is bit i (bit 0 least significant);
+ *     bit value 1 = up.  A fermion system of N sites uses 2N bits,
+ *     orbital k = 2*site + sigma (sigma 0 = up, 1 = down), i.e. the
+ *     4-ary site digit of Sec. 3.1 split with up in the low bit.
+ *   * Fermion signs use the Jordan-Wigner order ascending in k; a hop
+ *     c+_a c_b picks up (-1)^(number of occupied orbitals strictly
+ *     between a and b).
+ *   * A full-space index is the bit string itself; a sector index is
+ *     the rank of the bit string among the sector's bit strings in
+ *     ascending order (the order of the Sec. 3.3 example).
+ *   * Vectors are device memory in one of four storage types (hphi_dtype).
+ *     nvec > 1 vectors are interleaved: element b of row r is at
+ *     v[r * nvec + b].  Complex vectors store (re, im) pairs.
+ *   * Every call returns an int status (HPHI_OK = 0, negative = error).
+ *     Arguments are validated on the host before anything is launched;
+ *     on error nothing is written and hphi_last_error() (thread-local)
+ *     holds a message.  No exception crosses the ABI.
+ *   * Unless stated otherwise calls are asynchronous on the HIP stream
+ *     passed as `stream` (a hipStream_t; NULL = the legacy default stream).
+ *   * Handles (hphi_basis, hphi_ham) are library-owned and immutable
+ *     after build.  A hphi_ham holds a small reduction workspace:
+ *     calls that share one hphi_ham must not overlap in time on
+ *     different streams.
+ */
+#ifndef HPHI_H
+#define HPHI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    HPHI_OK = 0,
+    HPHI_EINVAL = -1,       /* bad argument (checked before any launch)            */
+    HPHI_ENOMEM = -2,       /* device or host allocation failed                   */
+    HPHI_EDEVICE = -3,      /* HIP runtime error (message in hphi_last_error)      */
+    HPHI_ESECTOR = -4,      /* a term maps a sector state outside the sector       */
+    HPHI_EDTYPE = -5,       /* complex matrix elements with a real storage type    */
+    HPHI_INFO_BREAKDOWN = 1 /* Lanczos stopped early: beta below tolerance or dim  */
+};
+
+enum { HPHI_SPIN_HALF = 0, HPHI_FERMION = 1 };
+
+enum {
+    HPHI_SECTOR_NONE = 0,     /* full 2^nbits space (grand canonical)            */
+    HPHI_SECTOR_SZ = 1,       /* spins: fixed 2*Sz = (#up - #down)              */
+    HPHI_SECTOR_NUP_NDN = 2,  /* fermions: fixed number of up and of down        */
+    HPHI_SECTOR_NTOT = 3      /* fermions: fixed total particle number           */
+};
+
+typedef enum {
+    HPHI_F64 = 0,   /* real double                                               */
+    HPHI_C128 = 1,  /* complex double (re, im)                                   */
+    HPHI_F32 = 2,   /* real float storage: FP32 row sums, FP64 reductions        */
+    HPHI_C64 = 3    /* complex float storage (re, im), as HPHI_F32               */
+} hphi_dtype;
+
+/* ------------------------------------------------------------------ basis */
+
+/* Hilbert-space descriptor (Sec. 3.1).
+ *   particle   HPHI_SPIN_HALF (nbits = n_sites) or HPHI_FERMION (nbits = 2*n_sites)
+ *   sector     HPHI_SECTOR_*; two_sz for SZ (parity of n_sites), n_up/n_dn for
+ *              NUP_NDN, n_tot for NTOT
+ *   split_bits width of the low half of the split rank tables (0 = nbits/2,
+ *              rounded down to even for fermions so a site is never split).
+ * Limits: full space nbits <= 40; sector spaces nbits <= 62 with
+ * 2^split_bits and 2^(nbits - split_bits) table entries each <= 2^26. */
+typedef struct {
+    int32_t particle;
+    int32_t n_sites;
+    int32_t sector;
+    int32_t two_sz;
+    int32_t n_up;
+    int32_t n_dn;
+    int32_t n_tot;
+    int32_t split_bits;
+} hphi_basis_desc;
+
+typedef struct hphi_basis hphi_basis;
+
+/* Build the space and, for a sector, the split rank tables of the
+ * two-dimensional search (Sec. 3.1): for a bit string s = (h << b_lo) | l,
+ *   index(s) = J_hi[h] + J_lo[l],
+ * J_lo[l] = rank of l among low halves with the same charge, J_hi[h] = index
+ * of the first sector state with high half h.  Tables are enumerated on the
+ * host with the same-popcount successor and copied to the current device.
+ * Synchronous.  *out receives a handle to free with hphi_basis_free. */
+int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out);
+
+/* Dimension of the space (host value). */
+int hphi_basis_dim(const hphi_basis* basis, int64_t* dim);
+
+/* Device arrays, n entries each.  rank: idx[k] = index of cfg[k] or -1 if
+ * cfg[k] is not in the space.  unrank: cfg[k] = configuration of idx[k];
+ * indices outside [0, dim) give cfg = ~0. */
+int hphi_basis_rank(const hphi_basis* basis, const uint64_t* cfg, int64_t* idx, int64_t n,
+                    void* stream);
+int hphi_basis_unrank(const hphi_basis* basis, const int64_t* idx, uint64_t* cfg, int64_t n,
+                      void* stream);
+
+void hphi_basis_free(hphi_basis* basis);
+
+/* ------------------------------------------------------------ Hamiltonian */
+
+enum {
+    /* spins (Sec. 2.3 "Spin"): site indices i != j < n_sites                    */
+    HPHI_TERM_SPIN_BOND = 0,   /* sum_ab c[3a+b] S_i^a S_j^b, a,b in (x,y,z)     */
+    HPHI_TERM_SPIN_FIELD = 1,  /* sum_a c[a] S_i^a                                */
+    /* fermions (Sec. 2.3 "Fermion Hubbard"): orbital indices < 2*n_sites        */
+    HPHI_TERM_HOP = 2,         /* t c+_i c_j + conj(t) c+_j c_i, t = c[0] + i c[1], i != j */
+    HPHI_TERM_DENS = 3,        /* c[0] n_i n_j, i != j                             */
+    HPHI_TERM_NUM = 4,         /* c[0] n_i                                         */
+    HPHI_TERM_HUBBARD_U = 5    /* c[0] n_{i,up} n_{i,down}, i a site index         */
+};
+
+/* One term of the Hamiltonian.  Unused fields are ignored.  Each term is
+ * Hermitian on its own; the Hamiltonian is the sum of the list as given
+ * (an undirected bond is listed once). */
+typedef struct {
+    int32_t kind;
+    int32_t i;
+    int32_t j;
+    int32_t reserved;
+    double c[9];
+} hphi_term;
+
+typedef struct hphi_ham hphi_ham;
+
+/* Validate and pack terms for the on-the-fly product (Sec. 3.3): each term
+ * becomes per-bit-pattern diagonal values and, per flip mask, the pulled
+ * matrix elements <s|H|s ^ mask>.  Returns HPHI_ESECTOR if a term has a
+ * nonzero element that leaves the basis' sector (e.g. a transverse field or
+ * a Kitaev coupling on an Sz sector), HPHI_EINVAL for bad indices.
+ * The basis must outlive the ham.  Synchronous. */
+int hphi_ham_build(const hphi_basis* basis, const hphi_term* terms, int64_t n_terms,
+                   hphi_ham** out);
+
+/* 1 if any matrix element is complex (then only C128/C64 storage is allowed). */
+int hphi_ham_is_complex(const hphi_ham* ham, int32_t* is_complex);
+
+void hphi_ham_free(hphi_ham* ham);
+
+/* ------------------------------------------------------------------ H . v */
+
+/* Options of hphi_hv.  With x_b = s_b * v_b (s_b = in_scale[b], or 1):
+ *     u_b = a * (H x_b) + b * x_b
+ * and, if reduce != NULL, FP64 sums written to reduce[q * nvec + b]:
+ *     q = 0: <x_b|x_b>   q = 1: Re<x_b|H x_b>   q = 2: <H x_b|H x_b>   q = 3: <u_b|u_b>
+ * reduced in a fixed order (bitwise reproducible for a fixed launch shape).
+ * u may be NULL (reductions only). */
+typedef struct {
+    double a;
+    double b;
+    const double* in_scale; /* device [nvec] or NULL */
+    double* reduce;         /* device [4 * nvec] or NULL */
+} hphi_hv_opts;
+
+/* Matrix-free product over all rows of the space.  v, u: device, dim*nvec
+ * elements of `dtype`, interleaved; u must not alias v.  nvec in
+ * {1, 2, 4, 8, 16}.  FP32/C64 storage: loads convert to FP32 arithmetic
+ * with FP32 coefficients; reductions are FP64.  opts NULL = {1, 0, NULL, NULL}.
+ * Returns HPHI_EDTYPE for a complex Hamiltonian with a real dtype. */
+int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+            const hphi_hv_opts* opts, void* stream);
+
+/* Element export from the same device code that hphi_hv uses (parity checks).
+ * For rows row0 .. row0+nrows-1, writes up to `cap` elements per row:
+ *   the diagonal (col = row, term_id = -1, value = sum of diagonal parts) if nonzero,
+ *   then one entry per packed off-diagonal operator whose element is nonzero
+ *   (col = target index, term_id = index into the term list, value = signed
+ *   matrix element <row|H|col>).
+ * cols/re/im/term_id: device [nrows * cap]; counts: device [nrows], the full
+ * element count of each row (may exceed cap; extra elements are dropped). */
+int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap,
+                     int64_t* cols, double* re, double* im, int32_t* term_id, int32_t* counts,
+                     void* stream);
+
+/* ---------------------------------------------------------------- Lanczos */
+
+typedef struct {
+    int32_t n_iter;        /* number of Lanczos steps (size of T_n), >= 1        */
+    int32_t dtype;         /* storage type of the Lanczos vectors                */
+    int32_t refine;        /* 1: second pass for the eigenvector + FP64 check    */
+    int32_t use_graph;     /* 1: replay the iteration from a captured HIP graph  */
+    double breakdown_tol;  /* relative beta tolerance, <= 0 selects 1e-13        */
+} hphi_lanczos_opts;
+
+typedef struct {
+    double* alpha;         /* host, caller-owned [n_iter]: alpha_k               */
+    double* beta;          /* host, caller-owned [n_iter]: beta[k] = beta_{k+1}  */
+    int32_t n_done;        /* steps taken (size of T)                            */
+    int32_t info;          /* HPHI_OK or HPHI_INFO_BREAKDOWN                      */
+    double e0_ritz;        /* lowest eigenvalue of T_n                           */
+    double e0_refined;     /* <x|H|x>/<x|x> of the eigenvector, FP64 (refine)    */
+    double variance;       /* <H^2> - <H>^2 of x (refine)                        */
+    double residual;       /* |Hx - E x| / |x| (refine)                          */
+} hphi_lanczos_result;
+
+/* Lanczos ground state (Sec. 3.4): v_0 = x_0/|x_0|, beta_0 = 0,
+ *   alpha_k = (H v_k, v_k), w = H v_k - beta_k v_{k-1} - alpha_k v_k,
+ *   beta_{k+1} = |w|, v_{k+1} = w / beta_{k+1},
+ * two stored vectors, no reorthogonalization; the lowest Ritz value of T_n
+ * comes from a host FP64 tridiagonal eigensolver.  The recurrence stops
+ * early (info = HPHI_INFO_BREAKDOWN) when k+1 reaches the dimension or
+ * beta_{k+1} <= tol * max(|alpha_k|, beta_k, 1).  With refine, the
+ * recurrence is replayed bit-for-bit to accumulate x = sum_k e~_k v_k in
+ * FP64 (App. A.3) and E, variance and residual are measured with an FP64
+ * product.
+ *   hams[n_hams]  one Hamiltonian per independent problem (e.g. Sz sectors)
+ *   v0[h]         device start vector, storage dtype, dim_h entries
+ *   work[h]       device scratch of 2 * dim_h storage elements
+ *   x_out[h]      device FP64 (C128 for complex dtypes) [dim_h], required if refine
+ *   res[h]        results; alpha/beta arrays of n_iter entries each
+ * Synchronizes `stream` before returning. */
+int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos_opts* opts,
+                 const void* const* v0, void* const* work, void* const* x_out,
+                 hphi_lanczos_result* res, void* stream);
+
+/* -------------------------------------------------------------------- TPQ */
+
+/* One microcanonical TPQ step (Sec. 3.5) for nvec independent samples:
+ * with psi = s * psi_in (s = in_scale[b] or 1),
+ *     phi = (l - H / N_s) psi,   psi_out = phi (unnormalized)
+ * and obs (device, [4 * nvec], layout obs[q * nvec + b]):
+ *     q = 0: u_{k-1}   = <psi|H|psi> / (<psi|psi> N_s)   energy per site of the input
+ *     q = 1: <H^2>/N_s^2 of the input state
+ *     q = 2: beta_{k-1} = (2 (k-1) / N_s) / (l - u_{k-1})
+ *     q = 3: 1 / |phi|, the scale that normalizes psi_out (pass &obs[3*nvec]
+ *            as in_scale of the next step)
+ * k >= 1 is the index of the produced state psi_k.  N_s = n_sites.
+ * psi_out must not alias psi_in. */
+int hphi_tpq_step(const hphi_ham* ham, const void* psi_in, void* psi_out, int64_t nvec,
+                  int32_t dtype, double l, int32_t k, const double* in_scale, double* obs,
+                  void* stream);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Message of the last error on this thread ("" if none). */
+const char* hphi_last_error(void);
+
+/* Library version string. */
+const char* hphi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPHI_H */

@@ -1,0 +1,22 @@
+"""MI355X-native matrix-free H.v / Lanczos / TPQ for spin-1/2 and fermion lattices.
+
+The computation lives in libhphi.so (HIP, gfx950) behind the C ABI of
+include/hphi.h; `binding` exposes the same entry points to Python with
+torch tensors as device memory.  There is no CPU fallback.
+"""
+
+from .binding import (  # noqa: F401
+    Basis,
+    Ham,
+    DTYPE_NAMES,
+    hphi_basis_build,
+    hphi_basis_rank,
+    hphi_basis_unrank,
+    hphi_ham_build,
+    hphi_hv,
+    hphi_hv_elements,
+    hphi_lanczos,
+    hphi_tpq_step,
+    version,
+)
+from ._lib import HphiError, LIB_PATH  # noqa: F401

@@ -1,0 +1,311 @@
+// C entry points: argument checks, the Lanczos driver (Sec. 3.4) and the
+// TPQ step (Sec. 3.5) on top of the product kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "hphi_internal.h"
+
+namespace hphi {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return HPHI_OK;
+    return set_error(e == hipErrorOutOfMemory ? HPHI_ENOMEM : HPHI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool valid_dtype(int dt) { return dt == HPHI_F64 || dt == HPHI_C128 || dt == HPHI_F32 || dt == HPHI_C64; }
+static bool valid_nvec(int64_t n) { return n == 1 || n == 2 || n == 4 || n == 8 || n == 16; }
+
+}  // namespace hphi
+
+using namespace hphi;
+
+extern "C" const char* hphi_last_error(void) { return g_err; }
+
+extern "C" const char* hphi_version(void) { return "hphi-mi355x 0.1 (gfx950)"; }
+
+extern "C" int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+                       const hphi_hv_opts* opts, void* stream) {
+    if (!ham || !v) return set_error(HPHI_EINVAL, "hphi_hv: null ham or v");
+    if (u && u == v) return set_error(HPHI_EINVAL, "hphi_hv: u must not alias v");
+    if (!valid_nvec(nvec)) return set_error(HPHI_EINVAL, "hphi_hv: nvec must be 1, 2, 4, 8 or 16");
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_hv: bad dtype %d", dtype);
+    if (ham->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_hv: complex Hamiltonian with real storage");
+    hphi_hv_opts o = opts ? *opts : hphi_hv_opts{1.0, 0.0, nullptr, nullptr};
+    if (!std::isfinite(o.a) || !std::isfinite(o.b)) return set_error(HPHI_EINVAL, "hphi_hv: non-finite a or b");
+    HvLaunch L{};
+    L.ham = ham;
+    L.v = v;
+    L.u = u;
+    L.y = nullptr;
+    L.cy = nullptr;
+    L.sx = o.in_scale;
+    L.a = o.a;
+    L.b = o.b;
+    L.nvec = int(nvec);
+    L.dtype = dtype;
+    L.stop = nullptr;
+    L.reduce_out = o.reduce;
+    return launch_hv(L, (hipStream_t)stream);
+}
+
+extern "C" int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap, int64_t* cols,
+                                double* re, double* im, int32_t* term_id, int32_t* counts, void* stream) {
+    if (!ham) return set_error(HPHI_EINVAL, "hphi_hv_elements: null ham");
+    if (row0 < 0 || nrows < 0 || row0 + nrows > ham->basis->dim)
+        return set_error(HPHI_EINVAL, "hphi_hv_elements: rows out of range");
+    if (cap < 1 || !cols || !re || !im || !term_id || !counts)
+        return set_error(HPHI_EINVAL, "hphi_hv_elements: bad output arrays");
+    if (nrows == 0) return HPHI_OK;
+    return launch_elements(ham, row0, nrows, cap, cols, re, im, term_id, counts, (hipStream_t)stream);
+}
+
+extern "C" int hphi_tpq_step(const hphi_ham* ham, const void* psi_in, void* psi_out, int64_t nvec, int32_t dtype,
+                             double l, int32_t k, const double* in_scale, double* obs, void* stream) {
+    if (!ham || !psi_in || !psi_out || !obs) return set_error(HPHI_EINVAL, "hphi_tpq_step: null argument");
+    if (psi_in == psi_out) return set_error(HPHI_EINVAL, "hphi_tpq_step: psi_out must not alias psi_in");
+    if (!valid_nvec(nvec)) return set_error(HPHI_EINVAL, "hphi_tpq_step: nvec must be 1, 2, 4, 8 or 16");
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_tpq_step: bad dtype");
+    if (ham->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_tpq_step: complex Hamiltonian with real storage");
+    if (k < 1 || !std::isfinite(l)) return set_error(HPHI_EINVAL, "hphi_tpq_step: need k >= 1 and finite l");
+    const double ns = double(ham->n_sites);
+    HvLaunch L{};
+    L.ham = ham;
+    L.v = psi_in;
+    L.u = psi_out;
+    L.sx = in_scale;
+    L.a = -1.0 / ns;
+    L.b = l;
+    L.nvec = int(nvec);
+    L.dtype = dtype;
+    L.reduce_out = ham->d_red;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = launch_hv(L, st);
+    if (rc) return rc;
+    return launch_tpq_obs(ham->d_red, obs, int(nvec), ns, l, k, st);
+}
+
+// ---------------------------------------------------------------- Lanczos
+
+namespace {
+
+struct LzDev {
+    LzScalars* sc = nullptr;
+    double* alpha = nullptr;
+    double* beta = nullptr;
+    double* evec = nullptr;
+    double* red = nullptr;
+    double* spart = nullptr;   // partials of the streaming kernels
+    void* mem = nullptr;
+};
+
+constexpr int kStreamGrid = 1024;
+
+int lz_alloc(LzDev& D, int n) {
+    const size_t bytes = 256 + 3 * size_t(n) * 8 + 64 * 8 + size_t(kStreamGrid) * 8 + 1024;
+    char* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return set_error(HPHI_ENOMEM, "hphi_lanczos: scalar workspace");
+    D.mem = p;
+    D.sc = (LzScalars*)p;
+    p += 256;
+    D.alpha = (double*)p;
+    p += size_t(n) * 8;
+    D.beta = (double*)p;
+    p += size_t(n) * 8;
+    D.evec = (double*)p;
+    p += size_t(n) * 8;
+    D.red = (double*)p;
+    p += 64 * 8;
+    D.spart = (double*)p;
+    return HPHI_OK;
+}
+
+int stream_grid_for(int64_t scalars) {
+    int64_t g = (scalars + 1023) / 1024;
+    if (g < 1) g = 1;
+    if (g > kStreamGrid) g = kStreamGrid;
+    return int(g);
+}
+
+// One Lanczos iteration: pass 1 (product, alpha) and pass 2 (update, beta).
+int lz_iteration(const hphi_ham* H, int dtype, void* X, void* Y, bool first, LzDev& D, void* acc, int grid,
+                 hipStream_t st) {
+    const int* stop = &D.sc->stop;
+    HvLaunch L{};
+    L.ham = H;
+    L.v = X;
+    L.u = Y;
+    L.y = first ? nullptr : Y;
+    L.cy = &D.sc->cy;
+    L.sx = &D.sc->s_cur;
+    L.a = 1.0;
+    L.b = 0.0;
+    L.nvec = 1;
+    L.dtype = dtype;
+    L.stop = stop;
+    L.reduce_out = D.red;
+    int rc = launch_hv(L, st);
+    if (rc) return rc;
+    rc = launch_lz_after_hv(D.sc, D.red, D.alpha, acc ? D.evec : nullptr, st);
+    if (rc) return rc;
+    rc = launch_lanczos_update(Y, X, H->basis->dim, dtype, &D.sc->c2, acc, &D.sc->ecoef, D.spart, grid, D.red, stop,
+                               st);
+    if (rc) return rc;
+    return launch_lz_after_update(D.sc, D.red, D.beta, D.alpha, st);
+}
+
+// Run the recurrence from v0 for n_max steps (pass 1 or the eigenvector pass).
+int lz_run(const hphi_ham* H, int dtype, const void* v0, void* A, void* B, LzDev& D, int n_max, double tol,
+           void* acc, bool use_graph, hipStream_t st) {
+    const int64_t dim = H->basis->dim;
+    const int64_t scalars = dim * (dtype_complex(dtype) ? 2 : 1);
+    const int grid = stream_grid_for(scalars);
+    int rc = launch_copy_norm(v0, A, dim, dtype, D.spart, grid, D.red, st);
+    if (rc) return rc;
+    rc = launch_lz_init(D.sc, D.red, tol, n_max, st);
+    if (rc) return rc;
+    rc = lz_iteration(H, dtype, A, B, true, D, acc, grid, st);
+    if (rc) return rc;
+    int k = 1;
+    if (use_graph && n_max >= 3) {
+        // capture iterations (odd, even) once and replay; the device-side step
+        // counter and stop flag make every replay advance the recurrence
+        hipStream_t cs;
+        rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
+        if (rc) return rc;
+        hipEvent_t ev;
+        (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        (void)hipEventRecord(ev, st);
+        (void)hipStreamWaitEvent(cs, ev, 0);
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (!rc) {
+            int r1 = lz_iteration(H, dtype, B, A, false, D, acc, grid, cs);
+            int r2 = r1 ? r1 : lz_iteration(H, dtype, A, B, false, D, acc, grid, cs);
+            hipError_t e = hipStreamEndCapture(cs, &g);
+            rc = r2 ? r2 : check_hip(e, "end capture");
+        }
+        if (!rc) rc = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+        for (; !rc && k + 2 <= n_max; k += 2) rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
+        (void)hipEventRecord(ev, cs);
+        (void)hipStreamWaitEvent(st, ev, 0);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamDestroy(cs);
+        (void)hipEventDestroy(ev);
+        if (rc) return rc;
+    }
+    for (; k < n_max; ++k) {
+        void* X = (k & 1) ? B : A;
+        void* Y = (k & 1) ? A : B;
+        rc = lz_iteration(H, dtype, X, Y, false, D, acc, grid, st);
+        if (rc) return rc;
+    }
+    return HPHI_OK;
+}
+
+}  // namespace
+
+extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos_opts* opts,
+                            const void* const* v0, void* const* work, void* const* x_out, hphi_lanczos_result* res,
+                            void* stream) {
+    if (!hams || n_hams < 1 || !opts || !v0 || !work || !res) return set_error(HPHI_EINVAL, "hphi_lanczos: null argument");
+    const hphi_lanczos_opts o = *opts;
+    if (o.n_iter < 1 || o.n_iter > 100000) return set_error(HPHI_EINVAL, "hphi_lanczos: n_iter out of range");
+    if (!valid_dtype(o.dtype)) return set_error(HPHI_EINVAL, "hphi_lanczos: bad dtype");
+    if (o.refine && !x_out) return set_error(HPHI_EINVAL, "hphi_lanczos: refine needs x_out");
+    for (int h = 0; h < n_hams; ++h) {
+        if (!hams[h] || !v0[h] || !work[h] || !res[h].alpha || !res[h].beta)
+            return set_error(HPHI_EINVAL, "hphi_lanczos: null entry for problem %d", h);
+        if (o.refine && !x_out[h]) return set_error(HPHI_EINVAL, "hphi_lanczos: null x_out for problem %d", h);
+        if (hams[h]->is_complex && !dtype_complex(o.dtype))
+            return set_error(HPHI_EDTYPE, "hphi_lanczos: complex Hamiltonian with real storage");
+    }
+    const double tol = o.breakdown_tol > 0 ? o.breakdown_tol : 1e-13;
+    hipStream_t st = (hipStream_t)stream;
+    const int x_dtype = dtype_complex(o.dtype) ? HPHI_C128 : HPHI_F64;
+
+    for (int h = 0; h < n_hams; ++h) {
+        const hphi_ham* H = hams[h];
+        const int64_t dim = H->basis->dim;
+        const int n_max = int(dim < o.n_iter ? dim : o.n_iter);
+        const size_t vbytes = size_t(dim) * dtype_size(o.dtype);
+        void* A = work[h];
+        void* Bv = (char*)work[h] + vbytes;
+        LzDev D;
+        int rc = lz_alloc(D, o.n_iter);
+        if (rc) return rc;
+        auto fail = [&](int code) {
+            (void)hipFree(D.mem);
+            return code;
+        };
+        rc = lz_run(H, o.dtype, v0[h], A, Bv, D, n_max, tol, nullptr, o.use_graph != 0, st);
+        if (rc) return fail(rc);
+        LzScalars sc{};
+        rc = check_hip(hipMemcpyAsync(&sc, D.sc, sizeof(sc), hipMemcpyDeviceToHost, st), "copy scalars");
+        if (!rc) rc = check_hip(hipMemcpyAsync(res[h].alpha, D.alpha, size_t(o.n_iter) * 8, hipMemcpyDeviceToHost, st), "copy alpha");
+        if (!rc) rc = check_hip(hipMemcpyAsync(res[h].beta, D.beta, size_t(o.n_iter) * 8, hipMemcpyDeviceToHost, st), "copy beta");
+        if (!rc) rc = check_hip(hipStreamSynchronize(st), "lanczos sync");
+        if (rc) return fail(rc);
+        const int n = sc.n_done;
+        res[h].n_done = n;
+        res[h].info = (sc.breakdown || n < o.n_iter) ? HPHI_INFO_BREAKDOWN : HPHI_OK;
+        for (int k = n; k < o.n_iter; ++k) {
+            res[h].alpha[k] = 0.0;
+            res[h].beta[k] = 0.0;
+        }
+        if (n < 1) return fail(set_error(HPHI_EINVAL, "hphi_lanczos: zero start vector for problem %d", h));
+        std::vector<double> evec(n);
+        res[h].e0_ritz = tridiag_lowest(res[h].alpha, res[h].beta, n, evec.data());
+        res[h].e0_refined = res[h].variance = res[h].residual = NAN;
+        if (o.refine) {
+            // second pass: replay the recurrence and accumulate x = sum_k e~_k v_k
+            rc = check_hip(hipMemcpyAsync(D.evec, evec.data(), size_t(n) * 8, hipMemcpyHostToDevice, st), "copy evec");
+            if (!rc) rc = launch_fill_zero(x_out[h], dim * int64_t(dtype_size(x_dtype)), st);
+            if (!rc) rc = lz_run(H, o.dtype, v0[h], A, Bv, D, n, tol, x_out[h], o.use_graph != 0, st);
+            if (rc) return fail(rc);
+            // FP64 check of x: <x|x>, <x|Hx>, |Hx|^2, then |Hx - E x|^2
+            HvLaunch L{};
+            L.ham = H;
+            L.v = x_out[h];
+            L.u = nullptr;
+            L.a = 1.0;
+            L.b = 0.0;
+            L.nvec = 1;
+            L.dtype = x_dtype;
+            L.reduce_out = D.red;
+            rc = launch_hv(L, st);
+            double q[4];
+            if (!rc) rc = check_hip(hipMemcpyAsync(q, D.red, 32, hipMemcpyDeviceToHost, st), "copy red");
+            if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
+            if (rc) return fail(rc);
+            const double E = q[1] / q[0];
+            res[h].e0_refined = E;
+            res[h].variance = q[2] / q[0] - E * E;
+            L.b = -E;
+            rc = launch_hv(L, st);
+            if (!rc) rc = check_hip(hipMemcpyAsync(q, D.red, 32, hipMemcpyDeviceToHost, st), "copy red");
+            if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
+            if (rc) return fail(rc);
+            res[h].residual = std::sqrt(q[3] / q[0]);
+        }
+        (void)hipFree(D.mem);
+    }
+    return HPHI_OK;
+}

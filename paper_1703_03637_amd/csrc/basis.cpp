@@ -1,0 +1,262 @@
+// Hilbert space and split rank tables (Sec. 3.1: canonical restricted space,
+// two-dimensional search, same-popcount successor).
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "hphi_internal.h"
+
+using namespace hphi;
+
+namespace {
+
+// Next larger integer with the same number of set bits (the "next higher
+// number with the same number of 1-bits" construction cited in Sec. 3.1).
+inline uint64_t same_popcount_successor(uint64_t x) {
+    uint64_t lowest = x & (~x + 1);
+    uint64_t ripple = x + lowest;
+    uint64_t ones = ((ripple ^ x) >> 2) / lowest;
+    return ripple | ones;
+}
+
+inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+constexpr uint64_t kEven = 0x5555555555555555ull;
+constexpr uint64_t kOdd = 0xAAAAAAAAAAAAAAAAull;
+
+struct Charge {
+    int sector;
+    int lo_bits;
+    // number of classes for the low half and class of a value
+    int n_classes() const {
+        if (sector == HPHI_SECTOR_NUP_NDN) return (lo_bits / 2 + 1) * (lo_bits / 2 + 1);
+        return lo_bits + 1;
+    }
+    int cls_lo(uint64_t l) const {
+        if (sector == HPHI_SECTOR_NUP_NDN) return popc(l & kEven) * (lo_bits / 2 + 1) + popc(l & kOdd);
+        return popc(l);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
+    if (!desc || !out) return set_error(HPHI_EINVAL, "hphi_basis_build: null argument");
+    *out = nullptr;
+    const hphi_basis_desc d = *desc;
+    if (d.particle != HPHI_SPIN_HALF && d.particle != HPHI_FERMION)
+        return set_error(HPHI_EINVAL, "hphi_basis_build: bad particle %d", d.particle);
+    if (d.n_sites < 1) return set_error(HPHI_EINVAL, "hphi_basis_build: n_sites must be >= 1");
+    const int nbits = d.particle == HPHI_SPIN_HALF ? d.n_sites : 2 * d.n_sites;
+    if (nbits > 62) return set_error(HPHI_EINVAL, "hphi_basis_build: %d bits exceed 62", nbits);
+
+    // target charge
+    int tgt_a = 0, tgt_b = 0;
+    switch (d.sector) {
+        case HPHI_SECTOR_NONE:
+            if (nbits > 40) return set_error(HPHI_EINVAL, "hphi_basis_build: full space limited to 40 bits");
+            break;
+        case HPHI_SECTOR_SZ:
+            if (d.particle != HPHI_SPIN_HALF)
+                return set_error(HPHI_EINVAL, "hphi_basis_build: SZ sector needs spins");
+            if (d.two_sz < -d.n_sites || d.two_sz > d.n_sites || ((d.n_sites + d.two_sz) & 1))
+                return set_error(HPHI_EINVAL, "hphi_basis_build: two_sz=%d impossible for %d sites",
+                                 d.two_sz, d.n_sites);
+            tgt_a = (d.n_sites + d.two_sz) / 2;
+            break;
+        case HPHI_SECTOR_NUP_NDN:
+            if (d.particle != HPHI_FERMION)
+                return set_error(HPHI_EINVAL, "hphi_basis_build: NUP_NDN sector needs fermions");
+            if (d.n_up < 0 || d.n_up > d.n_sites || d.n_dn < 0 || d.n_dn > d.n_sites)
+                return set_error(HPHI_EINVAL, "hphi_basis_build: n_up/n_dn out of range");
+            tgt_a = d.n_up;
+            tgt_b = d.n_dn;
+            break;
+        case HPHI_SECTOR_NTOT:
+            if (d.particle != HPHI_FERMION)
+                return set_error(HPHI_EINVAL, "hphi_basis_build: NTOT sector needs fermions");
+            if (d.n_tot < 0 || d.n_tot > 2 * d.n_sites)
+                return set_error(HPHI_EINVAL, "hphi_basis_build: n_tot out of range");
+            tgt_a = d.n_tot;
+            break;
+        default:
+            return set_error(HPHI_EINVAL, "hphi_basis_build: bad sector %d", d.sector);
+    }
+
+    hphi_basis* B = new (std::nothrow) hphi_basis();
+    if (!B) return set_error(HPHI_ENOMEM, "hphi_basis_build: host allocation");
+    B->desc = d;
+    B->nbits = nbits;
+    if (hipGetDevice(&B->device) != hipSuccess) {
+        delete B;
+        return set_error(HPHI_EDEVICE, "hphi_basis_build: no HIP device");
+    }
+    BasisDev& dv = B->dev;
+    dv.nbits = nbits;
+
+    if (d.sector == HPHI_SECTOR_NONE) {
+        B->dim = int64_t(1) << nbits;
+        dv.sector = 0;
+        dv.dim = B->dim;
+        dv.n_tiles = (B->dim + kTile - 1) / kTile;
+        *out = B;
+        return HPHI_OK;
+    }
+
+    int b_lo = d.split_bits;
+    if (b_lo == 0) {
+        b_lo = nbits / 2;
+        if (d.particle == HPHI_FERMION) b_lo &= ~1;
+        if (b_lo == 0) b_lo = d.particle == HPHI_FERMION ? 2 : 1;
+    }
+    if (b_lo < 1 || b_lo > nbits || (d.particle == HPHI_FERMION && (b_lo & 1))) {
+        delete B;
+        return set_error(HPHI_EINVAL, "hphi_basis_build: bad split_bits %d for %d bits", b_lo, nbits);
+    }
+    const int b_hi = nbits - b_lo;
+    if (b_lo > 26 || b_hi > 26) {
+        delete B;
+        return set_error(HPHI_EINVAL, "hphi_basis_build: split tables above 2^26 entries");
+    }
+    B->b_lo = b_lo;
+    B->b_hi = b_hi;
+    Charge ch{d.sector, b_lo};
+    const int ncls = ch.n_classes();
+    const uint64_t n_lo = uint64_t(1) << b_lo, n_hi = uint64_t(1) << b_hi;
+
+    // ---- low half: J_lo[l] = rank of l within its class; lows grouped by class
+    std::vector<uint32_t> cls_count(ncls, 0), cls_off(ncls + 1, 0);
+    B->j_lo.assign(n_lo, 0);
+    std::vector<uint32_t> lows(n_lo);
+    if (d.sector == HPHI_SECTOR_NUP_NDN) {
+        for (uint64_t l = 0; l < n_lo; ++l) B->j_lo[l] = cls_count[ch.cls_lo(l)]++;
+        for (int c = 0; c < ncls; ++c) cls_off[c + 1] = cls_off[c] + cls_count[c];
+        for (uint64_t l = 0; l < n_lo; ++l) lows[cls_off[ch.cls_lo(l)] + B->j_lo[l]] = uint32_t(l);
+    } else {
+        // popcount classes: enumerate each class in ascending order by the
+        // same-popcount successor
+        uint32_t off = 0;
+        for (int c = 0; c <= b_lo; ++c) {
+            cls_off[c] = off;
+            uint32_t r = 0;
+            if (c == 0) {
+                lows[off] = 0;
+                B->j_lo[0] = 0;
+                r = 1;
+            } else {
+                for (uint64_t x = (uint64_t(1) << c) - 1; x < n_lo; x = same_popcount_successor(x)) {
+                    lows[off + r] = uint32_t(x);
+                    B->j_lo[x] = r++;
+                }
+            }
+            cls_count[c] = r;
+            off += r;
+        }
+        cls_off[b_lo + 1] = off;
+    }
+
+    // ---- high half: valid highs, offsets, tiles
+    B->j_hi.assign(n_hi, -1);
+    std::vector<uint64_t> h_val;
+    std::vector<int64_t> h_row, h_tile;
+    std::vector<uint32_t> h_lobase;
+    int64_t offset = 0, tiles = 0;
+    const int hw = b_lo / 2 + 1;
+    for (uint64_t h = 0; h < n_hi; ++h) {
+        int need;
+        if (d.sector == HPHI_SECTOR_NUP_NDN) {
+            // high half starts at an even bit, so even/odd parity is preserved
+            int nu = tgt_a - popc(h & kEven), nd = tgt_b - popc(h & kOdd);
+            if (nu < 0 || nd < 0 || nu >= hw || nd >= hw) continue;
+            need = nu * hw + nd;
+        } else {
+            need = tgt_a - popc(h);
+            if (need < 0 || need > b_lo) continue;
+        }
+        const uint32_t cnt = cls_count[need];
+        if (cnt == 0) continue;
+        B->j_hi[h] = offset;
+        h_val.push_back(h);
+        h_row.push_back(offset);
+        h_tile.push_back(tiles);
+        h_lobase.push_back(cls_off[need]);
+        offset += cnt;
+        tiles += (cnt + kTile - 1) / kTile;
+    }
+    h_row.push_back(offset);
+    h_tile.push_back(tiles);
+    B->dim = offset;
+    if (offset == 0) {
+        delete B;
+        return set_error(HPHI_EINVAL, "hphi_basis_build: empty sector");
+    }
+
+    // ---- device copy (one allocation)
+    const size_t n_high = h_val.size();
+    size_t sz_jlo = align256(n_lo * 4), sz_jhi = align256(n_hi * 8), sz_hv = align256(n_high * 8),
+           sz_hr = align256((n_high + 1) * 8), sz_ht = align256((n_high + 1) * 8),
+           sz_hb = align256(n_high * 4), sz_lows = align256(n_lo * 4);
+    size_t total = sz_jlo + sz_jhi + sz_hv + sz_hr + sz_ht + sz_hb + sz_lows;
+    char* base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+        delete B;
+        return set_error(HPHI_ENOMEM, "hphi_basis_build: device allocation of %zu bytes", total);
+    }
+    B->dmem = base;
+    char* p = base;
+    auto put = [&](const void* src, size_t bytes, size_t stride) -> char* {
+        char* at = p;
+        if (bytes) (void)hipMemcpy(at, src, bytes, hipMemcpyHostToDevice);
+        p += stride;
+        return at;
+    };
+    dv.sector = d.sector;
+    dv.b_lo = b_lo;
+    dv.mask_lo = n_lo - 1;
+    dv.dim = offset;
+    dv.n_tiles = tiles;
+    dv.n_high = int64_t(n_high);
+    dv.j_lo = (const uint32_t*)put(B->j_lo.data(), n_lo * 4, sz_jlo);
+    dv.j_hi = (const int64_t*)put(B->j_hi.data(), n_hi * 8, sz_jhi);
+    dv.h_val = (const uint64_t*)put(h_val.data(), n_high * 8, sz_hv);
+    dv.h_row = (const int64_t*)put(h_row.data(), (n_high + 1) * 8, sz_hr);
+    dv.h_tile = (const int64_t*)put(h_tile.data(), (n_high + 1) * 8, sz_ht);
+    dv.h_lobase = (const uint32_t*)put(h_lobase.data(), n_high * 4, sz_hb);
+    dv.lows = (const uint32_t*)put(lows.data(), n_lo * 4, sz_lows);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        delete B;
+        return check_hip(e, "hphi_basis_build: table upload");
+    }
+    *out = B;
+    return HPHI_OK;
+}
+
+extern "C" int hphi_basis_dim(const hphi_basis* b, int64_t* dim) {
+    if (!b || !dim) return set_error(HPHI_EINVAL, "hphi_basis_dim: null argument");
+    *dim = b->dim;
+    return HPHI_OK;
+}
+
+extern "C" void hphi_basis_free(hphi_basis* b) {
+    if (!b) return;
+    if (b->dmem) (void)hipFree(b->dmem);
+    delete b;
+}
+
+extern "C" int hphi_basis_rank(const hphi_basis* b, const uint64_t* cfg, int64_t* idx, int64_t n,
+                               void* stream) {
+    if (!b || n < 0 || (n > 0 && (!cfg || !idx))) return set_error(HPHI_EINVAL, "hphi_basis_rank: bad argument");
+    if (n == 0) return HPHI_OK;
+    return launch_rank(b, cfg, idx, n, (hipStream_t)stream);
+}
+
+extern "C" int hphi_basis_unrank(const hphi_basis* b, const int64_t* idx, uint64_t* cfg, int64_t n,
+                                 void* stream) {
+    if (!b || n < 0 || (n > 0 && (!cfg || !idx))) return set_error(HPHI_EINVAL, "hphi_basis_unrank: bad argument");
+    if (n == 0) return HPHI_OK;
+    return launch_unrank(b, idx, cfg, n, (hipStream_t)stream);
+}

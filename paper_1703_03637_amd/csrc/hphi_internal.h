@@ -1,0 +1,151 @@
+// Internal data layout shared by the host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hphi.h"
+
+namespace hphi {
+
+// Rows per tile: one wavefront of 64 lanes, one row per lane.
+constexpr int kTile = 64;
+constexpr int kBlock = 256;              // threads per block (4 wavefronts)
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kMaxGrid = 4096;           // blocks of the persistent H.v grid
+constexpr int kMaxNvec = 16;
+constexpr int kNQ = 4;                   // reduced quantities per vector
+
+// One packed operator of the on-the-fly product (Sec. 3.3).
+//
+// The row pattern p = bit(s, bi) | bit(s, bj) << 1 selects the diagonal
+// contribution d[p] and the pulled off-diagonal element
+//   <s| H_term |s ^ xmask> = (cr[p] + i ci[p]) * (-1)^popcount(s & smask).
+// xmask == 0 marks a diagonal-only operator.  smask is nonzero only for
+// fermion hops (orbitals strictly between the two ends).
+struct DevOp {
+    uint64_t xmask;
+    uint64_t smask;
+    uint32_t bi;
+    uint32_t bj;
+    int32_t term;
+    int32_t has_off;      // any nonzero off-diagonal element
+    double d[4];
+    double cr[4];
+    double ci[4];
+    float fr[4];
+    float fi[4];
+};
+
+// Device view of a basis, passed by value to kernels.
+struct BasisDev {
+    int32_t sector;       // 0 = full space (index = bit string)
+    int32_t nbits;
+    int32_t b_lo;         // width of the low half of the split tables
+    int32_t pad;
+    uint64_t mask_lo;
+    int64_t dim;
+    int64_t n_tiles;      // tiles of kTile rows
+    int64_t n_high;       // valid high halves (sector only)
+    const uint32_t* j_lo;     // [2^b_lo]   rank of a low half within its charge class
+    const int64_t* j_hi;      // [2^b_hi]   first index of a high half, -1 if none
+    const uint64_t* h_val;    // [n_high]   valid high halves, ascending
+    const int64_t* h_row;     // [n_high+1] first row of each high half (prefix)
+    const int64_t* h_tile;    // [n_high+1] first tile of each high half (prefix)
+    const uint32_t* h_lobase; // [n_high]   offset of its low list in `lows`
+    const uint32_t* lows;     // low halves grouped by charge class, ascending
+};
+
+}  // namespace hphi
+
+struct hphi_basis {
+    hphi_basis_desc desc;
+    int nbits = 0;
+    int b_lo = 0;
+    int b_hi = 0;
+    int64_t dim = 0;
+    int device = 0;
+    hphi::BasisDev dev{};
+    void* dmem = nullptr;
+    // host copies (validation and host-side rank checks)
+    std::vector<uint32_t> j_lo;
+    std::vector<int64_t> j_hi;
+};
+
+struct hphi_ham {
+    const hphi_basis* basis = nullptr;
+    int n_sites = 0;
+    bool is_complex = false;
+    std::vector<hphi::DevOp> ops;
+    hphi::DevOp* d_ops = nullptr;
+    int grid = 0;                 // persistent grid of the product kernels
+    double* d_partials = nullptr; // [kMaxGrid][kNQ * kMaxNvec]
+    double* d_red = nullptr;      // [kNQ * kMaxNvec]
+};
+
+namespace hphi {
+
+// error state (thread-local message)
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+
+// launch wrappers (kernels.hip)
+struct HvLaunch {
+    const hphi_ham* ham;
+    const void* v;
+    void* u;
+    const void* y;           // optional extra input (may alias u), coefficient cy[b]
+    const double* cy;        // device [nvec]
+    const double* sx;        // device [nvec] or nullptr
+    double a, b;
+    int nvec;
+    int dtype;
+    const int* stop;         // device flag: skip all work if nonzero (nullptr = never)
+    double* reduce_out;      // device [kNQ * nvec] or nullptr (quantity-major)
+};
+int launch_hv(const HvLaunch& L, hipStream_t st);
+int launch_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int cap, int64_t* cols,
+                    double* re, double* im, int32_t* term, int32_t* counts, hipStream_t st);
+int launch_rank(const hphi_basis* b, const uint64_t* cfg, int64_t* idx, int64_t n, hipStream_t st);
+int launch_unrank(const hphi_basis* b, const int64_t* idx, uint64_t* cfg, int64_t n, hipStream_t st);
+
+// Lanczos / TPQ support kernels
+int launch_copy_norm(const void* src, void* dst, int64_t n, int dtype, double* partials, int grid,
+                     double* red, hipStream_t st);
+int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const double* c2,
+                          void* acc, const double* ecoef, double* partials, int grid, double* red,
+                          const int* stop, hipStream_t st);
+int launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k,
+                   hipStream_t st);
+
+// per-iteration scalar bookkeeping of the Lanczos recurrence (device, one thread)
+struct LzScalars {
+    double s_cur;     // scale of the stored v_k (1/beta_k folded into loads)
+    double cy;        // coefficient of v_{k-1} in pass 1: -beta_k * s_prev
+    double c2;        // coefficient of v_k in pass 2: -alpha_k * s_cur
+    double ecoef;     // eigenvector coefficient e~_k * s_cur (second pass)
+    double beta_k;    // beta_k of the current step
+    double tol;
+    int32_t k;        // current step
+    int32_t n_max;    // min(n_iter, dim)
+    int32_t stop;     // 1 once the recurrence has ended
+    int32_t n_done;
+    int32_t breakdown;
+    int32_t pad;
+};
+int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipStream_t st);
+int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec,
+                       hipStream_t st);
+int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st);
+
+// host tridiagonal eigensolver (tridiag.cpp)
+double tridiag_lowest(const double* alpha, const double* beta, int n, double* evec);
+
+size_t dtype_size(int dtype);
+bool dtype_complex(int dtype);
+
+}  // namespace hphi

@@ -1,0 +1,377 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: element lists (indices, term ids, signs) bit-exact; FP64 H.v within
+1e-12 relative, norm-wise and component-wise against |H||v|; FP32 storage
+within a bound derived from FP32 rounding; reductions, Lanczos and TPQ
+against the oracle's literal recurrences.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from synth import lattices as L
+from synth.configs import BasisDesc, workload, kh_honeycomb_terms
+from synth.vectors import gaussian_vectors, uniform_vectors
+from oracle import basis as ob
+from oracle import hamiltonian as oh
+from oracle import solvers as osv
+
+pytestmark = pytest.mark.gpu
+
+import paper_1703_03637_amd as hp  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    print(f"[gpu] {torch.cuda.get_device_name(0)} lib={hp.LIB_PATH}", flush=True)
+
+
+SMALL_CASES = {
+    "spin_full_complex": (BasisDesc("spin", 7),
+                          lambda: L.random_spin_terms(7, 10, 101, conserve_sz=False, fields=True, real=False)),
+    "spin_full_real": (BasisDesc("spin", 8),
+                       lambda: L.random_spin_terms(8, 12, 102, conserve_sz=False, fields=True, real=True)),
+    "spin_sz_dm": (BasisDesc("spin", 10, "sz", two_sz=2),
+                   lambda: L.random_spin_terms(10, 14, 103, conserve_sz=True, fields=True, real=False)),
+    "spin_sz_split3": (BasisDesc("spin", 11, "sz", two_sz=-1, split_bits=3),
+                       lambda: L.random_spin_terms(11, 15, 104, conserve_sz=True, real=True)),
+    "ferm_nupndn": (BasisDesc("fermion", 5, "nupndn", n_up=2, n_dn=3),
+                    lambda: L.random_fermion_terms(5, 12, 105, conserve_spin=True, real=False, n_dens=3,
+                                                   with_mu=True)),
+    "ferm_full": (BasisDesc("fermion", 3),
+                  lambda: L.random_fermion_terms(3, 8, 106, conserve_spin=False, real=False, n_dens=2,
+                                                 with_mu=True)),
+    "ferm_ntot": (BasisDesc("fermion", 4, "ntot", n_tot=3),
+                  lambda: L.random_fermion_terms(4, 10, 107, conserve_spin=False, real=True, n_dens=2)),
+    "hubbard_3x3": (BasisDesc("fermion", 9, "nupndn", n_up=3, n_dn=4),
+                    lambda: L.hubbard_terms(L.rect_bonds(3, 3), 9, t=1.0, U=8.0)),
+    "kh_honeycomb12": (BasisDesc("spin", 12), lambda: kh_honeycomb_terms(lx=3, ly=2, random_dirs=False)),
+    "ring4": (BasisDesc("spin", 4), lambda: [L.heisenberg_bond(i, j) for i, j in L.chain_bonds(4)]),
+}
+
+
+def _case(name):
+    desc, mk = SMALL_CASES[name]
+    terms = mk()
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    return desc, terms, basis, ham
+
+
+def _gpu_elements(ham, rows0, nrows, cap=64):
+    cols, re, im, term, counts = hp.hphi_hv_elements(ham, rows0, nrows, cap)
+    cols, re, im, term, counts = (x.cpu().numpy() for x in (cols, re, im, term, counts))
+    assert counts.max() <= cap
+    out = []
+    for r in range(nrows):
+        d = {}
+        for k in range(counts[r]):
+            key = (int(cols[r, k]), int(term[r, k]))
+            assert key not in d, "duplicate (col, term) from one row"
+            d[key] = complex(re[r, k], im[r, k])
+        out.append(d)
+    return out
+
+
+def _compare_elements(gpu, ora, exact_values):
+    for r, (g, o) in enumerate(zip(gpu, ora)):
+        assert g.keys() == o.keys(), f"row {r}: index/term sets differ"
+        for key, val in o.items():
+            gv = g[key]
+            if exact_values:
+                assert gv == val, f"row {r} {key}: {gv} != {val}"
+            else:
+                assert abs(gv - val) <= 4e-16 * max(1.0, abs(val)), f"row {r} {key}: {gv} vs {val}"
+            # signs are integer data: bit-exact
+            assert np.sign(gv.real) == np.sign(val.real) and np.sign(gv.imag) == np.sign(val.imag)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_element_lists_match_oracle(name):
+    print(f"[gpu] elements {name}", flush=True)
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    assert basis.dim == len(st)
+    gpu = _gpu_elements(ham, 0, basis.dim)
+    ora = oh.row_elements(desc, terms, np.arange(len(st)), st)
+    ora = [ora[i] for i in range(len(st))]
+    fermion = desc.particle == "fermion"
+    _compare_elements(gpu, ora, exact_values=fermion)
+
+
+def test_element_lists_chain16_rows():
+    w = workload("heis_chain16")
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    rows = [0, 1, 12345, 40000, 65535]
+    for r in rows:
+        g = _gpu_elements(ham, r, 1)[0]
+        o = oh.row_elements_sampled(w.basis, w.terms, np.array([r], np.uint64), lambda x: x.astype(np.int64))[0]
+        _compare_elements([g], [o], exact_values=True)
+
+
+def test_element_lists_hubbard_4x3_sampled_rows():
+    w = workload("hubbard_4x3")
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    st = ob.states(w.basis)
+    assert basis.dim == len(st) == 853776
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([[0, 1, len(st) - 1], rng.integers(0, len(st), 200)])
+    ora = oh.row_elements_sampled(w.basis, w.terms, st[rows], lambda x: ob.rank(st, x))
+    for r, o in zip(rows, ora):
+        g = _gpu_elements(ham, int(r), 1)[0]
+        _compare_elements([g], [o], exact_values=True)
+
+
+def _abs_bound(desc, terms, st, v):
+    H = oh.sparse_h(desc, terms, st)
+    Ha = abs(H)
+    return Ha @ np.abs(v), H
+
+
+def _to_dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+@pytest.mark.parametrize("nvec", [1, 4, 16])
+def test_hv_fp64_matches_oracle(name, nvec):
+    print(f"[gpu] hv fp64 {name} nvec={nvec}", flush=True)
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    cplx = ham.is_complex or nvec == 4
+    v = uniform_vectors(len(st), list(range(7, 7 + nvec)), cplx)
+    dt = torch.complex128 if cplx else torch.float64
+    vd = _to_dev(v if cplx else v.real, dt)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    u = hp.hphi_hv(ham, vd).cpu().numpy().reshape(len(st), nvec)
+    bound, H = _abs_bound(desc, terms, st, v)
+    ref = H @ v
+    err = np.abs(u - ref)
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref) + 1e-300
+    assert np.all(err <= 1e-12 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["spin_sz_dm", "ferm_nupndn", "kh_honeycomb12", "hubbard_3x3"])
+@pytest.mark.parametrize("nvec", [1, 8])
+def test_hv_fp32_storage(name, nvec):
+    """FP32 storage: loads, coefficients and row sums in FP32; bound = 8 eps32 (|H||v|) per element."""
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(20, 20 + nvec)), True)
+    dt = torch.complex64
+    if not ham.is_complex and nvec == 1:
+        v = v.real.copy()
+        dt = torch.float32
+    vd = _to_dev(v, dt)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    v32 = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    u = hp.hphi_hv(ham, vd).cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    bound, H = _abs_bound(desc, terms, st, v32)
+    ref = H @ v32
+    n_terms = max(8, len(terms))
+    assert np.all(np.abs(u - ref) <= n_terms * 6e-8 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("nvec", [1, 2, 16])
+def test_hv_epilogue_and_reductions(nvec):
+    desc, terms, basis, ham = _case("spin_sz_dm")
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(30, 30 + nvec)), True)
+    vd = _to_dev(v, torch.complex128)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    scale = torch.tensor(np.linspace(0.5, 2.0, nvec), dtype=torch.float64, device="cuda")
+    red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+    a, b = -0.37, 1.25
+    u = hp.hphi_hv(ham, vd, a=a, b=b, in_scale=scale, reduce=red).cpu().numpy().reshape(len(st), nvec)
+    H = oh.sparse_h(desc, terms, st)
+    x = v * scale.cpu().numpy()[None, :]
+    hx = H @ x
+    ref = a * hx + b * x
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+    red = red.cpu().numpy().reshape(4, nvec)
+    for bb in range(nvec):
+        want = [np.vdot(x[:, bb], x[:, bb]).real, np.vdot(x[:, bb], hx[:, bb]).real,
+                np.vdot(hx[:, bb], hx[:, bb]).real, np.vdot(ref[:, bb], ref[:, bb]).real]
+        assert np.allclose(red[:, bb], want, rtol=1e-12, atol=0)
+    # reduce-only mode (no output vector) gives the same sums
+    red2 = torch.empty_like(torch.from_numpy(red.reshape(-1))).cuda()
+    hp.hphi_hv(ham, vd, a=a, b=b, in_scale=scale, reduce=red2, write=False)
+    assert np.array_equal(red2.cpu().numpy().reshape(4, nvec), red)
+
+
+def test_batched_rows_bitwise_equal_single():
+    """Interleaved batch: each vector's output equals its single-vector product bit for bit."""
+    desc, terms, basis, ham = _case("kh_honeycomb12")
+    v = uniform_vectors(basis.dim, list(range(40, 56)), True)
+    vd = _to_dev(v, torch.complex64)
+    ub = hp.hphi_hv(ham, vd).cpu()
+    for bb in (0, 5, 15):
+        us = hp.hphi_hv(ham, vd[:, bb].contiguous()).cpu()
+        assert torch.equal(ub[:, bb], us)
+
+
+@pytest.mark.parametrize("name", ["spin_sz_dm", "spin_sz_split3", "ferm_nupndn", "ferm_ntot", "hubbard_3x3"])
+def test_rank_unrank_round_trip(name):
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    idx = torch.arange(basis.dim, dtype=torch.int64, device="cuda")
+    cfg = hp.hphi_basis_unrank(basis, idx).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(cfg, st)
+    r = hp.hphi_basis_rank(basis, torch.from_numpy(st.astype(np.int64)).cuda()).cpu().numpy()
+    assert np.array_equal(r, np.arange(basis.dim))
+    nb = ob.n_bits(desc)
+    allst = np.arange(1 << nb, dtype=np.uint64)
+    outside = allst[~ob.in_sector(desc, allst)][:500]
+    r2 = hp.hphi_basis_rank(basis, torch.from_numpy(outside.astype(np.int64)).cuda()).cpu().numpy()
+    assert np.all(r2 == -1)
+    bad = hp.hphi_basis_unrank(basis, torch.tensor([-1, basis.dim], dtype=torch.int64, device="cuda")).cpu()
+    assert np.all(bad.numpy().astype(np.uint64) == np.uint64(2 ** 64 - 1))
+
+
+def test_error_paths():
+    desc = BasisDesc("spin", 12, "sz", two_sz=0)
+    basis = hp.hphi_basis_build(desc)
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_ham_build(basis, kh_honeycomb_terms(lx=3, ly=2, random_dirs=False))
+    assert e.value.code == -4      # ESECTOR: Kitaev pair flips leave the Sz sector
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_ham_build(basis, [L.Term(L.SPIN_FIELD, 0, -1, (0.3, 0.0, 0.0))])
+    assert e.value.code == -4
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_ham_build(basis, [L.heisenberg_bond(0, 0)])
+    assert e.value.code == -1
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_ham_build(basis, [L.Term(L.HOP, 0, 1, (1.0, 0.0))])
+    assert e.value.code == -1
+    dm = [L.Term(L.SPIN_BOND, 0, 1, (1.0, 0.4, 0.0, -0.4, 1.0, 0.0, 0.0, 0.0, 1.0))]
+    ham = hp.hphi_ham_build(basis, dm)
+    assert ham.is_complex
+    v = torch.zeros(basis.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_hv(ham, v)
+    assert e.value.code == -5      # EDTYPE
+    vc = torch.zeros(basis.dim, 3, dtype=torch.complex128, device="cuda")
+    with pytest.raises(hp.HphiError) as e:
+        hp.hphi_hv(ham, vc)
+    assert e.value.code == -1      # nvec = 3
+    import ctypes as C
+    from paper_1703_03637_amd import _lib
+    vv = torch.zeros(basis.dim, dtype=torch.complex128, device="cuda")
+    rc = _lib.lib().hphi_hv(C.c_void_p(ham.handle), vv.data_ptr(), vv.data_ptr(), 1, _lib.HPHI_C128, None, None)
+    assert rc == -1                # u aliases v
+
+
+# ------------------------------------------------------------------ Lanczos
+
+def _lanczos_case(wname, dtype=torch.complex128, n_iter=None, use_graph=True):
+    w = workload(wname)
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    cplx = dtype.is_complex
+    x0 = gaussian_vectors(basis.dim, w.seeds[:1], cplx)[:, 0]
+    x0d = _to_dev(x0 if cplx else x0.real, dtype)
+    res = hp.hphi_lanczos([ham], [x0d], n_iter or w.n_iter, use_graph=use_graph)[0]
+    return w, basis, ham, x0d.cpu().numpy(), res
+
+
+def test_lanczos_ring4_breakdown_at_dim():
+    w, basis, ham, x0, res = _lanczos_case("heis_ring4", torch.float64, 16)
+    assert res["n_done"] <= 16 and res["info"] == 1
+    assert abs(res["e0_ritz"] - (-2.0)) < 1e-12
+    assert abs(res["e0_refined"] - (-2.0)) < 1e-12
+
+
+def test_lanczos_two_site_hubbard():
+    w, basis, ham, x0, res = _lanczos_case("hubbard_2site", torch.float64, 4)
+    assert abs(res["e0_ritz"] - (8 - np.sqrt(64 + 16)) / 2) < 1e-12
+
+
+def test_lanczos_chain16_matches_oracle_and_bethe():
+    w, basis, ham, x0, res = _lanczos_case("heis_chain16")
+    H = oh.sparse_h(w.basis, w.terms)
+    a, b = osv.lanczos(lambda v: H @ v, x0.astype(np.complex128), w.n_iter, basis.dim)
+    assert np.allclose(res["alpha"][:30], a[:30], rtol=0, atol=1e-10)
+    assert np.allclose(res["beta"][:30], b[:30], rtol=0, atol=1e-10)
+    e_bethe = -7.142296360616757
+    assert abs(res["e0_ritz"] - e_bethe) < 1e-10
+    assert abs(res["e0_refined"] - e_bethe) < 1e-10
+    assert res["residual"] < 1e-4
+
+
+def test_lanczos_graph_replay_is_bitwise_identical():
+    _, _, _, _, r1 = _lanczos_case("heis_chain12", n_iter=60, use_graph=True)
+    _, _, _, _, r2 = _lanczos_case("heis_chain12", n_iter=60, use_graph=False)
+    assert np.array_equal(r1["alpha"], r2["alpha"]) and np.array_equal(r1["beta"], r2["beta"])
+    assert r1["e0_refined"] == r2["e0_refined"]
+
+
+def test_lanczos_hubbard_3x3_vs_dense():
+    desc, terms, basis, ham = _case("hubbard_3x3")
+    H = oh.sparse_h(desc, terms)
+    e = np.linalg.eigvalsh(H.toarray())
+    x0 = gaussian_vectors(basis.dim, [77], False)[:, 0]
+    res = hp.hphi_lanczos([ham], [_to_dev(x0, torch.float64)], 150)[0]
+    assert abs(res["e0_ritz"] - e[0]) < 1e-10
+    assert abs(res["e0_refined"] - e[0]) < 1e-10
+    gap = e[1] - e[0]
+    assert abs(res["e0_refined"] - e[0]) <= res["residual"] ** 2 / gap + 1e-11
+
+
+def test_lanczos_fp32_storage_refined():
+    """FP32 vectors, FP64 recurrence scalars: the FP64 Rayleigh quotient of the rebuilt vector."""
+    w = workload("heis_chain12")
+    basis = hp.hphi_basis_build(BasisDesc("spin", 12, "sz", two_sz=0))
+    ham = hp.hphi_ham_build(basis, w.terms)
+    H = oh.sparse_h(basis.desc, w.terms)
+    e = np.linalg.eigvalsh(H.toarray())
+    x0 = gaussian_vectors(basis.dim, [3], False)[:, 0]
+    res = hp.hphi_lanczos([ham], [_to_dev(x0, torch.float32)], 120)[0]
+    assert abs(res["e0_ritz"] - e[0]) < 1e-4
+    assert abs(res["e0_refined"] - e[0]) / abs(e[0]) < 1e-8
+
+
+def test_lanczos_multiple_problems():
+    w = workload("heis_chain12")
+    bases = [hp.hphi_basis_build(BasisDesc("spin", 12, "sz", two_sz=tz)) for tz in (0, 2, 10, 12)]
+    hams = [hp.hphi_ham_build(b, w.terms) for b in bases]
+    x0 = [_to_dev(gaussian_vectors(b.dim, [5 + k], False)[:, 0], torch.float64) for k, b in enumerate(bases)]
+    res = hp.hphi_lanczos(hams, x0, 80)
+    for b, r in zip(bases, res):
+        H = oh.sparse_h(b.desc, w.terms)
+        e0 = np.linalg.eigvalsh(H.toarray())[0]
+        assert abs(r["e0_ritz"] - e0) < 1e-9
+    assert res[-1]["n_done"] == 1 and res[-1]["info"] == 1
+    assert abs(res[-1]["e0_ritz"] - 12 / 4) < 1e-14
+
+
+# ---------------------------------------------------------------------- TPQ
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 2e-6)])
+def test_tpq_trajectory_matches_oracle(dtype, tol):
+    ns, l, steps, nvec = 12, 1.5, 40, 4
+    desc, terms, basis, ham = _case("kh_honeycomb12")
+    H = oh.sparse_h(desc, terms)
+    psi0 = gaussian_vectors(basis.dim, [20, 21, 22, 23], True)
+    a = _to_dev(psi0, dtype)
+    bbuf = torch.empty_like(a)
+    us = []
+    scale = None
+    for k in range(1, steps + 1):
+        o = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+        hp.hphi_tpq_step(ham, a, bbuf, l, k, scale, o)
+        us.append(o.cpu().numpy().reshape(4, nvec).copy())
+        a, bbuf = bbuf, a
+        scale = o[3 * nvec:4 * nvec]
+    us = np.array(us)
+    for bb in range(nvec):
+        u_ref, h2_ref, _ = osv.tpq(lambda v: H @ v, psi0[:, bb], ns, l, steps)
+        assert np.allclose(us[:, 0, bb], u_ref, rtol=0, atol=tol)
+        assert np.allclose(us[:, 1, bb], h2_ref, rtol=0, atol=tol)
+        assert np.allclose(us[:, 2, bb], osv.tpq_beta(u_ref, ns, l), rtol=0, atol=100 * tol)
