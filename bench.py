@@ -1,0 +1,197 @@
+"""Benchmark of the matrix-free H.v / TPQ hot path on one MI355X.
+
+Workload: Kitaev-Heisenberg model on the 24-site periodic honeycomb
+cluster (K = -1, J = 0.1, link directions drawn per link), full 2^24
+space, microcanonical TPQ (l = 1.5) with 16 samples interleaved in one
+batched product, complex64 storage, FP64 reductions and observables.
+One step = one batched TPQ step (16 H.v products + fused reductions).
+
+Also measured in the same run:
+  * the plain FP64 single-vector path (same Hamiltonian, one complex128
+    vector per step) in samples*iterations/s, and the energy of sample 0
+    after the timed steps from both paths (complex64 state re-evaluated
+    with an FP64 product);
+  * the product kernel alone, timed with HIP events on the stream it is
+    launched on, for the roofline (algorithmic bytes = dim * nvec * 16 B);
+  * the C oracle on a bounded row slice of the same workload (host cores).
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "H·v products/s and achieved HBM GB/s; batched mixed TPQ vs plain FP64 Lanczos"
+
+
+def _events_ms(fn, reps, torch):
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        fn()
+    end.record()
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def run_tpq(hp, ham, psi, steps, warmup, l, torch):
+    """Run warmup + timed TPQ steps; returns (ms per step, final buffers, obs of the last step)."""
+    a = psi
+    b = torch.empty_like(a)
+    nvec = 1 if a.dim() == 1 else a.shape[1]
+    obs = [torch.empty(4 * nvec, dtype=torch.float64, device="cuda") for _ in range(2)]
+    scale = None
+    k = 1
+
+    def step():
+        nonlocal a, b, scale, k
+        o = obs[k & 1]
+        hp.hphi_tpq_step(ham, a, b, l, k, scale, o)
+        a, b = b, a
+        scale = o[3 * nvec:4 * nvec]
+        k += 1
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    return ms, a, scale, obs[(k - 1) & 1], k - 1
+
+
+def cpu_baseline(w, terms, v_host, dim, nvec, target_s=12.0):
+    """The C oracle on a contiguous row slice, scaled to H.v products/s."""
+    import numpy as np
+    from oracle import c_oracle
+    rows = np.arange(0, 4096, dtype=np.uint64)
+    t0 = time.perf_counter()
+    c_oracle.rows_hv(terms, rows, v_host)
+    dt = time.perf_counter() - t0
+    n = int(min(dim, max(4096, 4096 * target_s / max(dt, 1e-6))))
+    rows = np.arange(0, n, dtype=np.uint64)
+    t0 = time.perf_counter()
+    c_oracle.rows_hv(terms, rows, v_host)
+    dt = time.perf_counter() - t0
+    rate = (n / dim) * nvec / dt
+    return {"value": rate, "unit": "H·v products/s", "cores": c_oracle.threads(), "kind": "oracle",
+            "sample": f"C oracle (hv_oracle.c, OpenMP) rows 0..{n - 1} of {dim} with {nvec} complex64 "
+                      f"vectors, {dt:.1f} s, scaled by dim/rows"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1703_03637_amd as hp
+    from synth.configs import workload
+    from synth.vectors import device_uniform
+
+    w = workload("kh_honeycomb24")
+    nvec, ns, l = w.nvec, w.basis.n_sites, w.tpq_l
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    dim = basis.dim
+
+    # ---- start vectors: seeded Gaussian, drawn on the device (one seed per sample)
+    def gauss(seed, n, dt):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        x = torch.randn((dim, n, 2), generator=g, device="cuda", dtype=torch.float64)
+        return torch.view_as_complex(x).to(dt).contiguous()
+
+    psi_b = torch.empty((dim, nvec), dtype=torch.complex64, device="cuda")
+    for bb, s in enumerate(w.seeds):
+        psi_b[:, bb] = gauss(s, 1, torch.complex64)[:, 0]
+    psi_1 = psi_b[:, 0].to(torch.complex128).contiguous()     # same psi_0 as sample 0
+
+    # ---- batched mixed-precision TPQ (headline)
+    ms_b, fin_b, scale_b, obs_b, k_b = run_tpq(hp, ham, psi_b, args.steps, args.warmup, l, torch)
+    # ---- plain FP64 single-vector TPQ (same Hamiltonian, same psi_0 as sample 0)
+    ms_1, fin_1, scale_1, obs_1, k_1 = run_tpq(hp, ham, psi_1, args.steps, args.warmup, l, torch)
+    assert k_b == k_1
+    # energy of sample 0 after the run: complex64 state evaluated with an FP64 product
+    x64 = fin_b[:, 0].to(torch.complex128).contiguous()
+    red = torch.empty(4, dtype=torch.float64, device="cuda")
+    hp.hphi_hv(ham, x64, reduce=red, write=False)
+    red = red.cpu().numpy()
+    u_mixed = red[1] / red[0] / ns
+    red1 = torch.empty(4, dtype=torch.float64, device="cuda")
+    hp.hphi_hv(ham, fin_1, reduce=red1, write=False)
+    red1 = red1.cpu().numpy()
+    u_fp64 = red1[1] / red1[0] / ns
+    rel_err = abs(u_mixed - u_fp64) / abs(u_fp64)
+
+    # ---- dominant kernel alone: the batched product, HIP events on its stream
+    out = torch.empty_like(psi_b)
+    sc = torch.ones(nvec, dtype=torch.float64, device="cuda")
+
+    def hv_once():
+        hp.hphi_hv(ham, psi_b, out, a=-1.0 / ns, b=l, in_scale=sc)
+
+    hv_once()
+    torch.cuda.synchronize()
+    k_ms = _events_ms(hv_once, args.kernel_reps, torch)
+    alg_bytes = dim * nvec * 8 * 2                      # read v once, write u once (complex64)
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+
+    value = nvec / (ms_b * 1e-3)                        # H.v products per second
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "H·v products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_b,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "kh_honeycomb24_tpq_b16_c64", "model": "Kitaev-Heisenberg honeycomb",
+                   "n_sites": ns, "dim": dim, "nvec": nvec, "K": -1.0, "J": 0.1, "tpq_l": l,
+                   "storage": "complex64", "reductions": "fp64"},
+        "hbm_gbps_step": alg_bytes / (ms_b * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "hv_kernel<float,complex,real-coef,full,16>", "kernel_ms": k_ms,
+                     "algorithmic_bytes": alg_bytes},
+        "fp64_single_vector": {"ms_per_step": ms_1, "samples_iterations_per_s": 1.0 / (ms_1 * 1e-3),
+                               "batched_samples_iterations_per_s": value,
+                               "speedup": value * ms_1 * 1e-3},
+        "energy_check": {"step": k_b, "u_mixed_fp64_eval": u_mixed, "u_fp64_path": u_fp64,
+                         "rel_err": rel_err, "gate": 1e-8},
+    }
+    if not args.no_cpu:
+        v_host = psi_b.cpu().numpy()
+        res["cpu_baseline"] = cpu_baseline(w, w.terms, v_host, dim, nvec)
+        res["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
