@@ -128,6 +128,11 @@ def main():
         psi_b[:, bb] = gauss(s, 1, torch.complex64)[:, 0]
     psi_1 = psi_b[:, 0].to(torch.complex128).contiguous()     # same psi_0 as sample 0
 
+    # ---- schedule autotuning (set-up, outside the timed region)
+    sched_b = hp.hphi_hv_tune(ham, psi_b)
+    sched_1 = hp.hphi_hv_tune(ham, psi_1)
+    torch.cuda.empty_cache()
+
     # ---- batched mixed-precision TPQ (headline)
     ms_b, fin_b, scale_b, obs_b, k_b = run_tpq(hp, ham, psi_b, args.steps, args.warmup, l, torch)
     # ---- plain FP64 single-vector TPQ (same Hamiltonian, same psi_0 as sample 0)
@@ -178,9 +183,10 @@ def main():
         "hbm_gbps_step": alg_bytes / (ms_b * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "hv_kernel<float,complex,real-coef,full,16>", "kernel_ms": k_ms,
-                     "algorithmic_bytes": alg_bytes},
+                     "kernel": "one batched product call (windowed hvw_kernel passes or hv_kernel)",
+                     "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes, "schedule": sched_b},
         "fp64_single_vector": {"ms_per_step": ms_1, "samples_iterations_per_s": 1.0 / (ms_1 * 1e-3),
+                               "schedule": sched_1,
                                "batched_samples_iterations_per_s": value,
                                "speedup": value * ms_1 * 1e-3},
         "energy_check": {"step": k_b, "u_mixed_fp64_eval": u_mixed, "u_fp64_path": u_fp64,

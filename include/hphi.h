@@ -70,7 +70,7 @@ enum {
 typedef enum {
     HPHI_F64 = 0,   /* real double                                               */
     HPHI_C128 = 1,  /* complex double (re, im)                                   */
-    HPHI_F32 = 2,   /* real float storage: FP32 row sums, FP64 reductions        */
+    HPHI_F32 = 2,   /* real float storage; products, sums, reductions in FP64    */
     HPHI_C64 = 3    /* complex float storage (re, im), as HPHI_F32               */
 } hphi_dtype;
 
@@ -176,11 +176,30 @@ typedef struct {
 
 /* Matrix-free product over all rows of the space.  v, u: device, dim*nvec
  * elements of `dtype`, interleaved; u must not alias v.  nvec in
- * {1, 2, 4, 8, 16}.  FP32/C64 storage: loads convert to FP32 arithmetic
- * with FP32 coefficients; reductions are FP64.  opts NULL = {1, 0, NULL, NULL}.
+ * {1, 2, 4, 8, 16}.  FP32/C64 are storage formats only: every product,
+ * row sum and reduction is FP64 with FP64 coefficients, and results are
+ * rounded once when stored (a multi-pass schedule also rounds the partial
+ * sums it passes between passes).  opts NULL = {1, 0, NULL, NULL}.
  * Returns HPHI_EDTYPE for a complex Hamiltonian with a real dtype. */
 int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
             const hphi_hv_opts* opts, void* stream);
+
+/* Autotuner of the product's launch schedule.  Times candidate schedules of
+ * hphi_hv on the caller's buffers (v: input, u: scratch output of the same
+ * size, overwritten) -- for full-space bases of 6..32 bits the windowed
+ * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes, or
+ * a single natural-order pass; lanes per row (nvec >= 8); resident blocks
+ * per CU -- and pins the fastest for this (ham, nvec, dtype): later
+ * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
+ * it.  Results are bitwise reproducible for a fixed schedule; a different
+ * schedule may change the last bits of the reductions.  sched_out (host,
+ * may be NULL) receives 6 ints: windowed, window_kb, max_passes,
+ * lanes_per_row, blocks_per_cu, microseconds per product call.  If the
+ * environment variable HPHI_TUNE_CACHE names a file, the choice is
+ * appended there and reused by later processes for the same device,
+ * space and operators.  Synchronizes `stream`. */
+int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+                 int32_t* sched_out, void* stream);
 
 /* Element export from the same device code that hphi_hv uses (parity checks).
  * For rows row0 .. row0+nrows-1, writes up to `cap` elements per row:

@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     hphi_ham_build,
     hphi_hv,
     hphi_hv_elements,
+    hphi_hv_tune,
     hphi_lanczos,
     hphi_tpq_step,
     version,

@@ -73,6 +73,7 @@ _SIGS = {
     "hphi_ham_free": ([C.c_void_p], None),
     "hphi_hv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(HvOptsC),
                  C.c_void_p], C.c_int),
+    "hphi_hv_tune": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_hv_elements": ([C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_lanczos": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(LanczosOptsC),

@@ -67,7 +67,10 @@ class Basis:
 
     def __del__(self):
         if getattr(self, "handle", None):
-            L.lib().hphi_basis_free(C.c_void_p(self.handle))
+            try:
+                L.lib().hphi_basis_free(C.c_void_p(self.handle))
+            except Exception:      # interpreter shutdown: the process frees everything
+                pass
             self.handle = None
 
 
@@ -115,7 +118,10 @@ class Ham:
 
     def __del__(self):
         if getattr(self, "handle", None):
-            L.lib().hphi_ham_free(C.c_void_p(self.handle))
+            try:
+                L.lib().hphi_ham_free(C.c_void_p(self.handle))
+            except Exception:      # interpreter shutdown: the process frees everything
+                pass
             self.handle = None
 
 
@@ -167,6 +173,17 @@ def hphi_hv(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None, *, a: f
     check(L.lib().hphi_hv(C.c_void_p(ham.handle), _ptr(v), _ptr(u), nv, _dtype_code(v), C.byref(opts),
                           _stream()))
     return u
+
+
+def hphi_hv_tune(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None) -> dict:
+    """Autotune the product schedule for v's nvec and dtype; returns the chosen schedule."""
+    nv = _nvec(v, ham.dim)
+    if u is None:
+        u = torch.empty_like(v)
+    out = (C.c_int32 * 6)()
+    check(L.lib().hphi_hv_tune(C.c_void_p(ham.handle), _ptr(v), _ptr(u), nv, _dtype_code(v), out, _stream()))
+    keys = ("windowed", "window_kb", "max_passes", "lanes_per_row", "blocks_per_cu", "us")
+    return dict(zip(keys, list(out)))
 
 
 def hphi_hv_elements(ham: Ham, row0: int, nrows: int, cap: int):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,8 +37,52 @@ struct DevOp {
     double d[4];
     double cr[4];
     double ci[4];
-    float fr[4];
-    float fi[4];
+};
+
+// Launch schedule of the product kernels (chosen by hphi_hv_tune or by
+// defaults).  Zero fields mean "default".
+struct Schedule {
+    int windowed = 1;       // windowed full-space kernel when it applies
+    int window_kb = 2048;   // L2 budget per XCD for a window block
+    int max_passes = 3;     // passes of the windowed kernel (1 = natural order)
+    int lpr = 0;            // lanes per row (nvec >= 8); 0 = default
+    int blocks_per_cu = 0;  // resident blocks per CU; 0 = as many as fit
+};
+
+// Compact kernel-side operator of the windowed product (configurations of
+// at most 32 bits), FP64 values.  Element for row
+// pattern p = bit(s,bi) | bit(s,bj) << 1: (c[p] + i ci[p]) times the sign
+// (-1)^popcount(s & sm); diagonal part d[p].  xm == 0 marks a padding or
+// diagonal-only entry.
+template <typename T>
+struct alignas(128) KOp {
+    uint32_t xm;
+    uint32_t sm;
+    uint32_t bi;
+    uint32_t bj;
+    T c[4];
+    T ci[4];
+    T d[4];
+};
+
+// Pass plan of the windowed full-space product.  Each pass applies the
+// operators whose flip bits all lie in its window of `wbits` configuration
+// bits; the window bits are placed in the low bits of the processing
+// index, so every partner row of a pass lies inside an L2-sized block of
+// rows that is processed at the same time.
+struct PassPlan {
+    int row_bytes = 0;
+    int window_kb = 0;              // L2 budget the window was sized for
+    int max_passes = 0;             // operators of further windows are folded back
+    int n_pass = 0;
+    int wbits = 0;
+    std::vector<int32_t> perm;      // [n_pass][64]: processing-index bit -> configuration bit
+    std::vector<int32_t> op_begin;  // [n_pass + 1] ranges into the pass-ordered operator list
+    DevOp* d_ops = nullptr;         // operators ordered by pass
+    int32_t* d_perm = nullptr;      // device copy of perm
+    // compact operators, each pass padded to a multiple of 4 entries
+    std::vector<int32_t> kop_begin; // [n_pass + 1]
+    KOp<double>* d_kop64 = nullptr;
 };
 
 // Device view of a basis, passed by value to kernels.
@@ -76,6 +121,7 @@ struct hphi_basis {
 };
 
 struct hphi_ham {
+    ~hphi_ham();
     const hphi_basis* basis = nullptr;
     int n_sites = 0;
     bool is_complex = false;
@@ -84,6 +130,13 @@ struct hphi_ham {
     int grid = 0;                 // persistent grid of the product kernels
     double* d_partials = nullptr; // [kMaxGrid][kNQ * kMaxNvec]
     double* d_red = nullptr;      // [kNQ * kMaxNvec]
+    std::mutex plan_mu;           // guards the lazily built pass plans and tuned schedules
+    std::vector<hphi::PassPlan*> plans;
+    struct Tuned {
+        int nvec, dtype;
+        hphi::Schedule s;
+    };
+    std::vector<Tuned> tuned;
 };
 
 namespace hphi {
@@ -105,7 +158,9 @@ struct HvLaunch {
     int dtype;
     const int* stop;         // device flag: skip all work if nonzero (nullptr = never)
     double* reduce_out;      // device [kNQ * nvec] or nullptr (quantity-major)
+    const Schedule* sched;   // nullptr: the tuned or default schedule
 };
+Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype);
 int launch_hv(const HvLaunch& L, hipStream_t st);
 int launch_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int cap, int64_t* cols,
                     double* re, double* im, int32_t* term, int32_t* counts, hipStream_t st);
@@ -141,6 +196,9 @@ int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipS
 int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec,
                        hipStream_t st);
 int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st);
+
+// pass plan of the windowed product (plan.cpp); nullptr if not applicable
+const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes);
 
 // host tridiagonal eigensolver (tridiag.cpp)
 double tridiag_lowest(const double* alpha, const double* beta, int n, double* evec);

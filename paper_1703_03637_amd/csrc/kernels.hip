@@ -19,6 +19,8 @@
 // a fixed-order second-stage kernel.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "hphi_internal.h"
 
 namespace hphi {
@@ -121,28 +123,6 @@ __device__ __forceinline__ void store_row(S* __restrict__ base, int64_t idx, con
     }
 }
 
-// Wavefront reduce-scatter of B values per lane: afterwards every lane L
-// holds the wave sum of x[L >> (6 - log2 B)].  Fixed exchange pattern.
-template <int B>
-__device__ __forceinline__ double wave_reduce_scatter(double (&x)[B], int lane) {
-    constexpr int LOGB = Log2<B>::value;
-#pragma unroll
-    for (int j = 0; j < LOGB; ++j) {
-        const int n = B >> j, half = n >> 1, off = 32 >> j;
-        const bool upper = (lane & off) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            const double send = upper ? x[i] : x[i + half];
-            const double keep = upper ? x[i + half] : x[i];
-            x[i] = keep + __shfl_xor(send, off, 64);
-        }
-    }
-    double r = x[0];
-#pragma unroll
-    for (int off = 32 >> LOGB; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
-    return r;
-}
-
 struct HvArgs {
     BasisDev bs;
     const DevOp* ops;
@@ -157,29 +137,148 @@ struct HvArgs {
     double* partials;
 };
 
+// the packed operator table seen through the constant address space
+typedef const __attribute__((address_space(4))) DevOp ConstOp;
+
+template <bool W64>
+struct StateT {
+    using type = uint32_t;
+};
+template <>
+struct StateT<true> {
+    using type = uint64_t;
+};
+
+// bit `pos` of a configuration (pos uniform across the wavefront)
+template <bool W64>
+__device__ __forceinline__ uint32_t bit_at(typename StateT<W64>::type s, uint32_t pos) {
+    if constexpr (W64) {
+        return uint32_t(s >> pos) & 1u;
+    } else {
+        return __builtin_amdgcn_ubfe(s, pos, 1u);
+    }
+}
+
+template <bool W64>
+__device__ __forceinline__ uint32_t parity_masked(typename StateT<W64>::type s, uint64_t m) {
+    if constexpr (W64) {
+        return uint32_t(__popcll(s & m)) & 1u;
+    } else {
+        return uint32_t(__popc(s & uint32_t(m))) & 1u;
+    }
+}
+
+// Reduce one quantity over the rows held by a wavefront.  Each lane holds
+// VPL per-row values (its share of the vectors); afterwards lane L holds the
+// wave sum for vector (L & (LPR-1)) * VPL + (L >> (6 - log2 VPL)).  The
+// first log2(VPL) exchange steps run in the storage precision (at most VPL
+// <= 16 products summed), the remaining steps and everything after in FP64.
+// branch-free choice between two values by a lane mask (all ones / zero):
+// a bitwise select, so no register array is ever indexed per lane
+__device__ __forceinline__ float pick(uint32_t m, float a, float b) {
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ __forceinline__ double pick(uint32_t m, double a, double b) {
+    const uint64_t mm = (uint64_t(m) << 32) | m;
+    const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    return __longlong_as_double(static_cast<long long>((ua & mm) | (ub & ~mm)));
+}
+
+template <typename R, int VPL, int LPR>
+__device__ __forceinline__ double wave_reduce_rows(R (&x)[VPL], int lane) {
+    constexpr int LOGV = Log2<VPL>::value;
+#pragma unroll
+    for (int j = 0; j < LOGV; ++j) {
+        const int half = (VPL >> j) >> 1, off = 32 >> j;
+        const uint32_t up = (lane & off) ? 0xffffffffu : 0u;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const R lo = x[i], hi = x[i + half];
+            const R send = pick(up, lo, hi);
+            const R keep = pick(up, hi, lo);
+            x[i] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+    double r = double(x[0]);
+#pragma unroll
+    for (int off = 32 >> LOGV; off >= LPR; off >>= 1) r += __shfl_xor(r, off, 64);
+    return r;
+}
+
+// The four per-row FP64 products (|x|^2, Re x*h, |h|^2, |u|^2) of this
+// lane's vectors, each reduced over the wavefront's rows into wq.
+template <int VPL, int LPR, int NC, int NE>
+__device__ __forceinline__ void wave_reduce_quantities(const double (&x)[NE], const double (&h)[NE],
+                                                       const double (&u)[NE], double (&wq)[kNQ], int lane) {
+    double q[VPL];
+#pragma unroll
+    for (int b = 0; b < VPL; ++b) {
+        q[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[b] += x[NC * b + c] * x[NC * b + c];
+    }
+    wq[0] += wave_reduce_rows<double, VPL, LPR>(q, lane);
+#pragma unroll
+    for (int b = 0; b < VPL; ++b) {
+        q[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[b] += x[NC * b + c] * h[NC * b + c];
+    }
+    wq[1] += wave_reduce_rows<double, VPL, LPR>(q, lane);
+#pragma unroll
+    for (int b = 0; b < VPL; ++b) {
+        q[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[b] += h[NC * b + c] * h[NC * b + c];
+    }
+    wq[2] += wave_reduce_rows<double, VPL, LPR>(q, lane);
+#pragma unroll
+    for (int b = 0; b < VPL; ++b) {
+        q[b] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[b] += u[NC * b + c] * u[NC * b + c];
+    }
+    wq[3] += wave_reduce_rows<double, VPL, LPR>(q, lane);
+}
+
 // S: storage scalar, CPLX: complex vectors, CCOEF: complex coefficients,
-// SECTOR: split-table rank, B: interleaved vectors per row.
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
+// SECTOR: split-table rank, B: interleaved vectors per row, LPR: lanes per
+// row (each lane owns B/LPR of the vectors), W64: configurations above 32 bits.
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
 __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
+    using ST = typename StateT<W64>::type;
     constexpr int NC = CPLX ? 2 : 1;
-    constexpr int NE = B * NC;
-    constexpr int LOGB = Log2<B>::value;
+    constexpr int VPL = B / LPR;          // vectors per lane
+    constexpr int NE = VPL * NC;          // scalars per lane per row
+    constexpr int RPW = 64 / LPR;         // rows per wavefront pass
+    constexpr int LOGV = Log2<VPL>::value;
+    constexpr int LOGL = Log2<LPR>::value;
+    static_assert(VPL * LPR == B, "LPR must divide B");
     if (A.stop && *A.stop) return;
 
     const int lane = threadIdx.x & 63;
+    const int sub = lane & (LPR - 1);      // which share of the vectors
+    const int rlane = lane >> LOGL;        // row within the pass
     const int wave = wave_uniform(threadIdx.x >> 6);
     const S* __restrict__ v = static_cast<const S*>(A.v);
     S* __restrict__ u = static_cast<S*>(A.u);
     const S* __restrict__ y = static_cast<const S*>(A.y);
-    const DevOp* __restrict__ ops = A.ops;
+    // operator table through the constant address space: uniform indices
+    // become scalar loads, per-lane pattern selects become v_cndmask
+    const ConstOp* ops = (const ConstOp*)(A.ops);
     const BasisDev& bs = A.bs;
+    const int n_ops = A.n_ops;
+    // element offset of this lane's share inside a row
+    const int64_t lane_off = int64_t(sub) * NE;
 
-    double sx[B], cy[B];
+    // all arithmetic in FP64: FP32 types are a storage format only
+    double sx[VPL], cy[VPL];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        sx[b] = A.sx ? A.sx[b] : 1.0;
-        cy[b] = (A.y && A.cy) ? A.cy[b] : 0.0;
+    for (int b = 0; b < VPL; ++b) {
+        sx[b] = A.sx ? A.sx[sub * VPL + b] : 1.0;
+        cy[b] = (A.y && A.cy) ? A.cy[sub * VPL + b] : 0.0;
     }
+    const double ca = A.a, cb = A.b;
 
     // XCD-aware tile range
     const int xcd = blockIdx.x & 7;
@@ -193,116 +292,129 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
 
     for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
-        int64_t row;
-        uint64_t s;
-        bool valid;
-        if constexpr (!SECTOR) {
-            row = tile * kTile + lane;
-            valid = row < bs.dim;
-            s = uint64_t(row);
-        } else {
-            const int64_t k = find_high(bs.h_tile, bs.n_high, tile);
-            const int64_t start = (tile - bs.h_tile[k]) * kTile + lane;
-            const int64_t cnt = bs.h_row[k + 1] - bs.h_row[k];
-            valid = start < cnt;
-            row = bs.h_row[k] + start;
-            s = valid ? ((bs.h_val[k] << bs.b_lo) | uint64_t(bs.lows[bs.h_lobase[k] + start])) : 0;
+        int64_t k_hi = 0, tile_row0 = 0, cnt = kTile;
+        ST hbits = 0;
+        uint32_t lobase = 0;
+        if constexpr (SECTOR) {
+            k_hi = find_high(bs.h_tile, bs.n_high, tile);
+            tile_row0 = (tile - bs.h_tile[k_hi]) * kTile;
+            cnt = bs.h_row[k_hi + 1] - bs.h_row[k_hi];
+            hbits = ST(bs.h_val[k_hi] << bs.b_lo);
+            lobase = bs.h_lobase[k_hi];
         }
+#pragma unroll 1
+        for (int pass = 0; pass < LPR; ++pass) {
+            const int r_in_tile = pass * RPW + rlane;
+            int64_t row;
+            ST s;
+            bool valid;
+            if constexpr (!SECTOR) {
+                row = tile * kTile + r_in_tile;
+                valid = row < bs.dim;
+                s = ST(row);
+            } else {
+                const int64_t start = tile_row0 + r_in_tile;
+                valid = start < cnt;
+                row = bs.h_row[k_hi] + start;
+                s = valid ? (hbits | ST(bs.lows[lobase + start])) : ST(0);
+            }
 
-        S acc[NE];
+            double acc[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) acc[e] = S(0);
-        double dsum = 0.0;
+            for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+            double dsum = 0.0;
 
-        if (valid) {
-            for (int o = 0; o < A.n_ops; ++o) {
-                const DevOp& op = ops[o];
-                const int p = int((s >> op.bi) & 1u) | (int((s >> op.bj) & 1u) << 1);
-                dsum += sel4(p, op.d[0], op.d[1], op.d[2], op.d[3]);
-                if (op.xmask == 0) continue;
-                S cr, ci;
-                if constexpr (sizeof(S) == 4) {
-                    cr = sel4(p, op.fr[0], op.fr[1], op.fr[2], op.fr[3]);
-                    ci = CCOEF ? sel4(p, op.fi[0], op.fi[1], op.fi[2], op.fi[3]) : 0.0f;
-                } else {
-                    cr = sel4(p, op.cr[0], op.cr[1], op.cr[2], op.cr[3]);
-                    ci = CCOEF ? sel4(p, op.ci[0], op.ci[1], op.ci[2], op.ci[3]) : 0.0;
-                }
-                const bool active = (cr != S(0)) || (CCOEF && ci != S(0));
-                if (active) {
-                    const uint64_t t = s ^ op.xmask;
-                    if (op.smask != 0 && (__popcll(s & op.smask) & 1)) {
-                        cr = -cr;
-                        ci = -ci;
+            if (valid) {
+                for (int o = 0; o < n_ops; ++o) {
+                    const ConstOp& op = ops[o];
+                    const uint32_t bi = op.bi, bj = op.bj;
+                    const uint64_t xmask = op.xmask, smask = op.smask;
+                    const bool b0 = bit_at<W64>(s, bi) != 0;
+                    const bool b1 = bit_at<W64>(s, bj) != 0;
+                    const double d0 = op.d[0], d1 = op.d[1], d2 = op.d[2], d3 = op.d[3];
+                    dsum += b1 ? (b0 ? d3 : d2) : (b0 ? d1 : d0);
+                    if (xmask == 0) continue;
+                    double cr, ci = 0.0;
+                    const double c0 = op.cr[0], c1 = op.cr[1], c2 = op.cr[2], c3 = op.cr[3];
+                    cr = b1 ? (b0 ? c3 : c2) : (b0 ? c1 : c0);
+                    if constexpr (CCOEF) {
+                        const double e0 = op.ci[0], e1 = op.ci[1], e2 = op.ci[2], e3 = op.ci[3];
+                        ci = b1 ? (b0 ? e3 : e2) : (b0 ? e1 : e0);
                     }
-                    const int64_t idx = rank_of<SECTOR>(bs, t);
-                    alignas(16) S g[NE];
-                    load_row<S, NE>(v, idx, g);
+                    const bool active = CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0);
+                    if (active) {
+                        const ST t = s ^ ST(xmask);
+                        if (smask != 0 && parity_masked<W64>(s, smask)) {
+                            cr = -cr;
+                            ci = -ci;
+                        }
+                        const int64_t idx = rank_of<SECTOR>(bs, uint64_t(t));
+                        alignas(16) S g[NE];
+                        load_row<S, NE>(v + lane_off, idx * LPR, g);
 #pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        if constexpr (CPLX) {
-                            const S gr = g[2 * b], gi = g[2 * b + 1];
-                            if constexpr (CCOEF) {
-                                acc[2 * b] += cr * gr - ci * gi;
-                                acc[2 * b + 1] += cr * gi + ci * gr;
+                        for (int b = 0; b < VPL; ++b) {
+                            if constexpr (CPLX) {
+                                const double gr = double(g[2 * b]), gi = double(g[2 * b + 1]);
+                                if constexpr (CCOEF) {
+                                    acc[2 * b] += cr * gr - ci * gi;
+                                    acc[2 * b + 1] += cr * gi + ci * gr;
+                                } else {
+                                    acc[2 * b] += cr * gr;
+                                    acc[2 * b + 1] += cr * gi;
+                                }
                             } else {
-                                acc[2 * b] += cr * gr;
-                                acc[2 * b + 1] += cr * gi;
+                                acc[b] += cr * double(g[b]);
                             }
-                        } else {
-                            acc[b] += cr * g[b];
                         }
                     }
                 }
             }
-        }
 
-        // epilogue: u = a * H x + b * x + cy * y with x = sx * v, in FP64
-        double q[kNQ][B];
-        if (valid) {
-            alignas(16) S vr[NE];
-            load_row<S, NE>(v, row, vr);
-            alignas(16) S yr[NE];
-            if (y) load_row<S, NE>(y, row, yr);
-            alignas(16) S ur[NE];
+            // epilogue: u = a * H x + b * x + cy * y with x = sx * v
+            double xr[NE], ur[NE];
+            if (valid) {
+                alignas(16) S vr[NE];
+                load_row<S, NE>(v + lane_off, row * LPR, vr);
+                if (y) {
+                    alignas(16) S yr[NE];
+                    load_row<S, NE>(y + lane_off, row * LPR, yr);
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if constexpr (CPLX) {
-                    const double xr = sx[b] * double(vr[2 * b]), xi = sx[b] * double(vr[2 * b + 1]);
-                    const double hr = sx[b] * (double(acc[2 * b]) + dsum * double(vr[2 * b]));
-                    const double hi = sx[b] * (double(acc[2 * b + 1]) + dsum * double(vr[2 * b + 1]));
-                    double ore = A.a * hr + A.b * xr, oim = A.a * hi + A.b * xi;
-                    if (y) {
-                        ore += cy[b] * double(yr[2 * b]);
-                        oim += cy[b] * double(yr[2 * b + 1]);
-                    }
-                    ur[2 * b] = S(ore);
-                    ur[2 * b + 1] = S(oim);
-                    q[0][b] = xr * xr + xi * xi;
-                    q[1][b] = xr * hr + xi * hi;
-                    q[2][b] = hr * hr + hi * hi;
-                    q[3][b] = ore * ore + oim * oim;
+                    for (int b = 0; b < VPL; ++b)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) ur[NC * b + c] = cy[b] * double(yr[NC * b + c]);
                 } else {
-                    const double x = sx[b] * double(vr[b]);
-                    const double h = sx[b] * (double(acc[b]) + dsum * double(vr[b]));
-                    double o = A.a * h + A.b * x;
-                    if (y) o += cy[b] * double(yr[b]);
-                    ur[b] = S(o);
-                    q[0][b] = x * x;
-                    q[1][b] = x * h;
-                    q[2][b] = h * h;
-                    q[3][b] = o * o;
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) ur[e] = 0.0;
+                }
+#pragma unroll
+                for (int b = 0; b < VPL; ++b)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        const int e = NC * b + c;
+                        const double vv = double(vr[e]);
+                        const double xv = sx[b] * vv;
+                        const double hv = sx[b] * (acc[e] + dsum * vv);
+                        acc[e] = hv;     // keep H x for the reductions
+                        xr[e] = xv;      // keep x for the reductions
+                        ur[e] += ca * hv + cb * xv;
+                    }
+                if (u) {
+                    alignas(16) S us[NE];
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
+                    store_row<S, NE>(u + lane_off, row * LPR, us);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    acc[e] = 0.0;
+                    xr[e] = 0.0;
+                    ur[e] = 0.0;
                 }
             }
-            if (u) store_row<S, NE>(u, row, ur);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kNQ; ++k)
-#pragma unroll
-                for (int b = 0; b < B; ++b) q[k][b] = 0.0;
+            // per-row products of the four reductions, one quantity at a time
+            wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
         }
-#pragma unroll
-        for (int k = 0; k < kNQ; ++k) wq[k] += wave_reduce_scatter<B>(q[k], lane);
     }
 
     __shared__ double sh[kWavesPerBlock][kNQ][64];
@@ -311,10 +423,226 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     __syncthreads();
     if (int(threadIdx.x) < kNQ * B) {
         const int k = threadIdx.x / B, b = threadIdx.x % B;
-        double s = 0.0;
+        const int bsub = b / VPL, bi = b % VPL;
+        const int L = (bi << (6 - LOGV)) | bsub;
+        double acc = 0.0;
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) s += sh[w][k][b << (6 - LOGB)];
-        A.partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = s;
+        for (int w = 0; w < kWavesPerBlock; ++w) acc += sh[w][k][L];
+        A.partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Windowed full-space product (one pass of a pass plan).
+//
+// Rows are visited in the order of a bit permutation of the row index: the
+// processing index q is scattered to the configuration s by perm[k] (q bit
+// k -> configuration bit).  The low bits of q are the pass's window, so
+// all partner rows s ^ xmask of the pass's operators lie within the block
+// of rows currently in flight.  mode bit 0: first pass (no partial sum to
+// read); bit 1: last pass (epilogue and reductions).  Partial sums of H v
+// (unscaled) travel through u between passes.
+struct HvwArgs {
+    const void* kops;    // KOp<S> records of this pass, a multiple of 4
+    int kop_begin;
+    int kop_end;
+    const int32_t* perm;
+    int nbits;
+    int mode;
+    int64_t n_tiles;
+    const void* v;
+    void* u;
+    const void* y;
+    const double* cy;
+    const double* sx;
+    double a, b;
+    const int* stop;
+    double* partials;
+};
+
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
+__global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
+    constexpr int NC = CPLX ? 2 : 1;
+    constexpr int VPL = B / LPR;
+    constexpr int NE = VPL * NC;
+    constexpr int RPW = 64 / LPR;
+    constexpr int LOGV = Log2<VPL>::value;
+    constexpr int LOGL = Log2<LPR>::value;
+    static_assert(VPL * LPR == B, "LPR must divide B");
+    if (A.stop && *A.stop) return;
+    const bool first = (A.mode & 1) != 0, last = (A.mode & 2) != 0;
+
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & (LPR - 1);
+    const int rlane = lane >> LOGL;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const S* __restrict__ v = static_cast<const S*>(A.v);
+    S* __restrict__ u = static_cast<S*>(A.u);
+    const S* __restrict__ y = static_cast<const S*>(A.y);
+    typedef const __attribute__((address_space(4))) KOp<double> ConstKOp;
+    const ConstKOp* kops = (const ConstKOp*)(A.kops);
+    typedef const __attribute__((address_space(4))) int32_t ConstI32;
+    const ConstI32* perm = (const ConstI32*)(A.perm);
+    const int64_t lane_off = int64_t(sub) * NE;
+
+    const int xcd = blockIdx.x & 7;
+    const int waves_x = int(gridDim.x >> 3) * kWavesPerBlock;
+    const int wl = int(blockIdx.x >> 3) * kWavesPerBlock + wave;
+    const int64_t T = A.n_tiles;
+    const int64_t Tx = (T + 7) >> 3;
+    const int64_t t_begin = xcd * Tx;
+    const int64_t t_end = (t_begin + Tx < T) ? t_begin + Tx : T;
+
+    double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
+        // configuration bits of the tile index (uniform)
+        uint32_t s_tile = 0;
+        for (int k = 6; k < A.nbits; ++k)
+            if ((tile >> (k - 6)) & 1) s_tile |= 1u << perm[k];
+#pragma unroll 1
+        for (int pass = 0; pass < LPR; ++pass) {
+            const int r = pass * RPW + rlane;      // position within the 64-row tile
+            uint32_t s = s_tile;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if ((r >> k) & 1) s |= 1u << perm[k];
+            const int64_t row = int64_t(s);
+
+            double acc[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+            double dsum = 0.0;
+            // operators in groups of 4: read the records, decode all, issue
+            // every gather, then accumulate (FP64 coefficients and sums)
+            for (int o = A.kop_begin; o < A.kop_end; o += 4) {
+                double crk[4], cik[4];
+                uint32_t tk[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const ConstKOp& rec = kops[o + k];
+                    const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj;
+                    const double rd0 = rec.d[0], rd1 = rec.d[1], rd2 = rec.d[2], rd3 = rec.d[3];
+                    const double rc0 = rec.c[0], rc1 = rec.c[1], rc2 = rec.c[2], rc3 = rec.c[3];
+                    const uint32_t b0 = __builtin_amdgcn_ubfe(s, bi, 1u);
+                    const uint32_t b1 = __builtin_amdgcn_ubfe(s, bj, 1u);
+                    const double d01 = b0 ? rd1 : rd0, d23 = b0 ? rd3 : rd2;
+                    dsum += b1 ? d23 : d01;
+                    const double c01 = b0 ? rc1 : rc0, c23 = b0 ? rc3 : rc2;
+                    double cr = b1 ? c23 : c01, ci = 0.0;
+                    if constexpr (CCOEF) {
+                        const double ri0 = rec.ci[0], ri1 = rec.ci[1], ri2 = rec.ci[2], ri3 = rec.ci[3];
+                        const double e01 = b0 ? ri1 : ri0, e23 = b0 ? ri3 : ri2;
+                        ci = b1 ? e23 : e01;
+                    }
+                    if (sm != 0) {
+                        const bool neg = (__popc(s & sm) & 1) != 0;
+                        cr = neg ? -cr : cr;
+                        ci = neg ? -ci : ci;
+                    }
+                    crk[k] = cr;
+                    cik[k] = ci;
+                    tk[k] = s ^ xm;
+                }
+                alignas(16) S g[4][NE];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                    if (act) {
+                        load_row<S, NE>(v + lane_off, int64_t(tk[k]) * LPR, g[k]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) g[k][e] = S(0);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double cr = crk[k], ci = cik[k];
+#pragma unroll
+                    for (int b = 0; b < VPL; ++b) {
+                        if constexpr (CPLX) {
+                            const double gr = double(g[k][2 * b]), gi = double(g[k][2 * b + 1]);
+                            if constexpr (CCOEF) {
+                                acc[2 * b] += cr * gr - ci * gi;
+                                acc[2 * b + 1] += cr * gi + ci * gr;
+                            } else {
+                                acc[2 * b] += cr * gr;
+                                acc[2 * b + 1] += cr * gi;
+                            }
+                        } else {
+                            acc[b] += cr * double(g[k][b]);
+                        }
+                    }
+                }
+            }
+
+            alignas(16) S vr[NE];
+            load_row<S, NE>(v + lane_off, row * LPR, vr);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) acc[e] += dsum * double(vr[e]);   // raw (unscaled) H v of this pass
+            if (!first) {
+                alignas(16) S pr[NE];
+                load_row<S, NE>(u + lane_off, row * LPR, pr);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) acc[e] += double(pr[e]);
+            }
+            if (!last) {
+                alignas(16) S ps[NE];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) ps[e] = S(acc[e]);
+                store_row<S, NE>(u + lane_off, row * LPR, ps);
+                continue;
+            }
+            double ur[NE], xr[NE];
+            if (y) {
+                alignas(16) S yr[NE];
+                load_row<S, NE>(y + lane_off, row * LPR, yr);
+#pragma unroll
+                for (int b = 0; b < VPL; ++b) {
+                    const double c = A.cy ? A.cy[sub * VPL + b] : 0.0;
+#pragma unroll
+                    for (int c2 = 0; c2 < NC; ++c2) ur[NC * b + c2] = c * double(yr[NC * b + c2]);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NE; ++e) ur[e] = 0.0;
+            }
+            const double ca = A.a, cb = A.b;
+#pragma unroll
+            for (int b = 0; b < VPL; ++b) {
+                const double sc = A.sx ? A.sx[sub * VPL + b] : 1.0;
+#pragma unroll
+                for (int c2 = 0; c2 < NC; ++c2) {
+                    const int e = NC * b + c2;
+                    const double xv = sc * double(vr[e]);
+                    const double hv = sc * acc[e];
+                    acc[e] = hv;
+                    xr[e] = xv;
+                    ur[e] += ca * hv + cb * xv;
+                }
+            }
+            if (u) {
+                alignas(16) S us[NE];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
+                store_row<S, NE>(u + lane_off, row * LPR, us);
+            }
+            wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
+        }
+    }
+    if (!last) return;
+    __shared__ double sh[kWavesPerBlock][kNQ][64];
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) sh[wave][k][lane] = wq[k];
+    __syncthreads();
+    if (int(threadIdx.x) < kNQ * B) {
+        const int k = threadIdx.x / B, b = threadIdx.x % B;
+        const int bsub = b / VPL, bi = b % VPL;
+        const int L = (bi << (6 - LOGV)) | bsub;
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) acc += sh[w][k][L];
+        A.partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = acc;
     }
 }
 
@@ -542,9 +870,43 @@ size_t dtype_size(int dtype) {
 
 bool dtype_complex(int dtype) { return dtype == HPHI_C128 || dtype == HPHI_C64; }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
-static int launch_hv_t(const HvLaunch& L, hipStream_t st) {
+// Persistent grid: the blocks that can be resident at once (capped by the
+// schedule's blocks per CU), so the tiles in flight on an XCD form one
+// contiguous front; a multiple of 8, capped by the work available.
+template <typename Kernel>
+static int occupancy_blocks(Kernel k) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+static int cu_count() {
+    static const int n = [] {
+        int dev = 0, ncu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        return ncu;
+    }();
+    return n;
+}
+
+static int make_grid(int occ, const Schedule& sc, int64_t tiles) {
+    int per_cu = occ;
+    if (sc.blocks_per_cu > 0 && sc.blocks_per_cu < per_cu) per_cu = sc.blocks_per_cu;
+    int64_t g = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t resident = int64_t(per_cu) * cu_count();
+    if (g > resident) g = resident;
+    if (g > kMaxGrid) g = kMaxGrid;
+    g = ((g + 7) / 8) * 8;
+    return int(g);
+}
+
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
+static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const hphi_ham* H = L.ham;
+    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64>);
+    const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
     HvArgs A;
     A.bs = H->basis->dev;
     A.ops = H->d_ops;
@@ -558,32 +920,117 @@ static int launch_hv_t(const HvLaunch& L, hipStream_t st) {
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
-    hv_kernel<S, CPLX, CCOEF, SECTOR, B><<<H->grid, kBlock, 0, st>>>(A);
+    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64><<<grid, kBlock, 0, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
     if (L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, H->grid, kNQ * B, L.reduce_out, L.stop);
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop);
         rc = check_hip(hipGetLastError(), "reduce launch");
     }
     return rc;
 }
 
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
+static int launch_hv_l(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
+    const bool w64 = L.ham->basis->nbits > 32;
+    if (w64) {
+        if constexpr (B <= 2) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
+        return set_error(HPHI_EINVAL, "nvec > 2 needs a space of at most 32 bits");
+    }
+    if constexpr (B >= 8) {
+        switch (sc.lpr) {
+            case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, false>(L, sc, st);
+            case 4: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false>(L, sc, st);
+        }
+    }
+    return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, false>(L, sc, st);
+}
+
 template <typename S, bool CPLX, bool CCOEF, bool SECTOR>
-static int launch_hv_b(const HvLaunch& L, hipStream_t st) {
+static int launch_hv_b(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     switch (L.nvec) {
-        case 1: return launch_hv_t<S, CPLX, CCOEF, SECTOR, 1>(L, st);
-        case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, 2>(L, st);
-        case 4: return launch_hv_t<S, CPLX, CCOEF, SECTOR, 4>(L, st);
-        case 8: return launch_hv_t<S, CPLX, CCOEF, SECTOR, 8>(L, st);
-        case 16: return launch_hv_t<S, CPLX, CCOEF, SECTOR, 16>(L, st);
+        case 1: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 1>(L, sc, st);
+        case 2: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 2>(L, sc, st);
+        case 4: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 4>(L, sc, st);
+        case 8: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 8>(L, sc, st);
+        case 16: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 16>(L, sc, st);
     }
     return set_error(HPHI_EINVAL, "nvec must be 1, 2, 4, 8 or 16 (got %d)", L.nvec);
 }
 
+// ---- windowed full-space launches
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
+static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, hipStream_t st) {
+    const hphi_ham* H = L.ham;
+    static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR>);
+    const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
+    HvwArgs A;
+    A.nbits = H->basis->nbits;
+    A.n_tiles = H->basis->dev.n_tiles;
+    A.v = L.v;
+    A.u = L.u;
+    A.y = L.y;
+    A.cy = L.cy;
+    A.sx = L.sx;
+    A.a = L.a;
+    A.b = L.b;
+    A.stop = L.stop;
+    A.partials = H->d_partials;
+    for (int p = 0; p < P->n_pass; ++p) {
+        A.kops = P->d_kop64;
+        A.kop_begin = P->kop_begin[p];
+        A.kop_end = P->kop_begin[p + 1];
+        A.perm = P->d_perm + size_t(p) * 64;
+        A.mode = (p == 0 ? 1 : 0) | (p == P->n_pass - 1 ? 2 : 0);
+        hvw_kernel<S, CPLX, CCOEF, B, LPR><<<grid, kBlock, 0, st>>>(A);
+        int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
+        if (rc) return rc;
+    }
+    if (L.reduce_out) {
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop);
+        return check_hip(hipGetLastError(), "reduce launch");
+    }
+    return HPHI_OK;
+}
+
+template <typename S, bool CPLX, bool CCOEF, int B>
+static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc, hipStream_t st) {
+    if constexpr (B >= 8) {
+        switch (sc.lpr) {
+            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2>(L, P, sc, st);
+            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4>(L, P, sc, st);
+        }
+    }
+    return launch_hvw_t<S, CPLX, CCOEF, B, 1>(L, P, sc, st);
+}
+
+// windowed product when it applies (full space, <= 32 bits, no in-place
+// extra input across several passes); returns 1 if not applicable
+template <typename S, bool CPLX, bool CCOEF>
+static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
+    const hphi_basis* Bs = L.ham->basis;
+    if (!sc.windowed || Bs->dev.sector != 0 || Bs->nbits > 32 || Bs->nbits < 6) return 1;
+    const int row_bytes = L.nvec * int(sizeof(S)) * (CPLX ? 2 : 1);
+    const PassPlan* P = get_plan(L.ham, row_bytes, sc.window_kb, sc.max_passes);
+    if (!P) return 1;
+    if (L.y && P->n_pass > 1) return 1;
+    switch (L.nvec) {
+        case 1: return launch_hvw_b<S, CPLX, CCOEF, 1>(L, P, sc, st);
+        case 2: return launch_hvw_b<S, CPLX, CCOEF, 2>(L, P, sc, st);
+        case 4: return launch_hvw_b<S, CPLX, CCOEF, 4>(L, P, sc, st);
+        case 8: return launch_hvw_b<S, CPLX, CCOEF, 8>(L, P, sc, st);
+        case 16: return launch_hvw_b<S, CPLX, CCOEF, 16>(L, P, sc, st);
+    }
+    return 1;
+}
+
 template <typename S, bool CPLX, bool CCOEF>
 static int launch_hv_s(const HvLaunch& L, hipStream_t st) {
-    if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true>(L, st);
-    return launch_hv_b<S, CPLX, CCOEF, false>(L, st);
+    const Schedule sc = L.sched ? *L.sched : schedule_for(L.ham, L.nvec, L.dtype);
+    const int w = try_launch_hvw<S, CPLX, CCOEF>(L, sc, st);
+    if (w != 1) return w;
+    if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true>(L, sc, st);
+    return launch_hv_b<S, CPLX, CCOEF, false>(L, sc, st);
 }
 
 int launch_hv(const HvLaunch& L, hipStream_t st) {

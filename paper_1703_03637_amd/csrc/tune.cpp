@@ -1,0 +1,208 @@
+// Schedule selection for the product kernels: defaults, the autotuner
+// (hphi_hv_tune) and its on-disk cache.
+//
+// The tuner times candidate schedules of the real product on the caller's
+// buffers -- window budget and number of passes of the windowed full-space
+// kernel (or the single-pass kernel), lanes per row, resident blocks per
+// CU -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
+// HPHI_TUNE_CACHE set, choices are appended to that file, keyed by a
+// signature of the device, the space and the packed operators, and are
+// reused by later processes without timing.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hphi_internal.h"
+
+namespace hphi {
+namespace {
+
+int env_int(const char* name, int dflt) {
+    const char* e = getenv(name);
+    return (e && *e) ? atoi(e) : dflt;
+}
+
+Schedule default_schedule(int nvec) {
+    Schedule s;
+    s.windowed = 1;
+    s.window_kb = 2048;
+    s.max_passes = 3;
+    s.lpr = nvec >= 16 ? 4 : (nvec >= 8 ? 2 : 1);
+    s.blocks_per_cu = 0;
+    // overrides for experiments
+    s.windowed = env_int("HPHI_WINDOWED", s.windowed);
+    s.window_kb = env_int("HPHI_L2_WINDOW_KB", s.window_kb);
+    s.max_passes = env_int("HPHI_PASSES", s.max_passes);
+    const int l = env_int("HPHI_LPR", 0);
+    if (nvec >= 8 && (l == 1 || l == 2 || l == 4)) s.lpr = l;
+    s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
+    if (s.window_kb < 1) s.window_kb = 2048;
+    if (s.max_passes < 1) s.max_passes = 1;
+    return s;
+}
+
+std::string signature(const hphi_ham* H, int nvec, int dtype) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ' || c == '|') c = '_';
+    uint64_t h = 1469598103934665603ull;   // FNV-1a over the packed operators
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(H->ops.data());
+    for (size_t i = 0; i < H->ops.size() * sizeof(DevOp); ++i) h = (h ^ p[i]) * 1099511628211ull;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|bits%d|sector%d|dim%lld|ops%zu|%016llx|nvec%d|dtype%d", arch.c_str(),
+             H->basis->nbits, H->basis->desc.sector, (long long)H->basis->dim, H->ops.size(),
+             (unsigned long long)h, nvec, dtype);
+    return buf;
+}
+
+bool cache_lookup(const std::string& sig, Schedule& out) {
+    const char* path = getenv("HPHI_TUNE_CACHE");
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        char key[300];
+        Schedule s;
+        if (sscanf(line, "%299s %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
+                   &s.blocks_per_cu) == 6 &&
+            sig == key) {
+            out = s;   // the last entry for a key wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& sig, const Schedule& s, double us) {
+    const char* path = getenv("HPHI_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
+            s.blocks_per_cu, us);
+    fclose(f);
+}
+
+}  // namespace
+
+Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype) {
+    hphi_ham* H = const_cast<hphi_ham*>(ham);
+    {
+        std::lock_guard<std::mutex> lock(H->plan_mu);
+        for (const auto& t : H->tuned)
+            if (t.nvec == nvec && t.dtype == dtype) return t.s;
+    }
+    Schedule s = default_schedule(nvec);
+    if (getenv("HPHI_TUNE_CACHE")) {
+        Schedule c;
+        if (cache_lookup(signature(H, nvec, dtype), c)) s = c;
+        std::lock_guard<std::mutex> lock(H->plan_mu);
+        H->tuned.push_back({nvec, dtype, s});
+    }
+    return s;
+}
+
+}  // namespace hphi
+
+using namespace hphi;
+
+extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+                            int32_t* sched_out, void* stream) {
+    if (!ham || !v || !u) return set_error(HPHI_EINVAL, "hphi_hv_tune: null argument");
+    if (u == v) return set_error(HPHI_EINVAL, "hphi_hv_tune: u must not alias v");
+    if (!(nvec == 1 || nvec == 2 || nvec == 4 || nvec == 8 || nvec == 16))
+        return set_error(HPHI_EINVAL, "hphi_hv_tune: nvec must be 1, 2, 4, 8 or 16");
+    if (dtype < HPHI_F64 || dtype > HPHI_C64) return set_error(HPHI_EINVAL, "hphi_hv_tune: bad dtype");
+    if (ham->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_hv_tune: complex Hamiltonian with real storage");
+    hipStream_t st = (hipStream_t)stream;
+    const hphi_basis* B = ham->basis;
+    const bool windowable = B->dev.sector == 0 && B->nbits >= 6 && B->nbits <= 32;
+
+    std::vector<Schedule> cands;
+    std::vector<int> lprs = {1};
+    if (nvec >= 8) lprs = {1, 2, 4};
+    for (int bpc : {0, 4}) {
+        for (int lpr : lprs) {
+            Schedule s;
+            s.lpr = lpr;
+            s.blocks_per_cu = bpc;
+            s.windowed = 0;
+            s.window_kb = 2048;
+            s.max_passes = 1;
+            cands.push_back(s);
+            if (!windowable) continue;
+            s.windowed = 1;
+            cands.push_back(s);   // single natural pass, compact operators
+            for (int wkb : {1024, 2048, 4096})
+                for (int mp : {2, 3}) {
+                    s.window_kb = wkb;
+                    s.max_passes = mp;
+                    cands.push_back(s);
+                }
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(HPHI_EDEVICE, "hphi_hv_tune: event creation failed");
+    double best_us = 1e300;
+    Schedule best = default_schedule(int(nvec));
+    for (const Schedule& s : cands) {
+        HvLaunch L{};
+        L.ham = ham;
+        L.v = v;
+        L.u = u;
+        L.a = 1.0;
+        L.b = 0.0;
+        L.nvec = int(nvec);
+        L.dtype = dtype;
+        L.sched = &s;
+        int rc = launch_hv(L, st);   // warm-up (builds the plan)
+        if (rc) continue;
+        (void)hipEventRecord(e0, st);
+        const int reps = 2;
+        for (int r = 0; r < reps && !rc; ++r) rc = launch_hv(L, st);
+        (void)hipEventRecord(e1, st);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) continue;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps;
+        if (us < best_us) {
+            best_us = us;
+            best = s;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_us >= 1e300) return set_error(HPHI_EDEVICE, "hphi_hv_tune: no schedule ran");
+    {
+        hphi_ham* H = const_cast<hphi_ham*>(ham);
+        std::lock_guard<std::mutex> lock(H->plan_mu);
+        bool set = false;
+        for (auto& t : H->tuned)
+            if (t.nvec == int(nvec) && t.dtype == dtype) {
+                t.s = best;
+                set = true;
+            }
+        if (!set) H->tuned.push_back({int(nvec), dtype, best});
+    }
+    cache_store(signature(ham, int(nvec), dtype), best, best_us);
+    if (sched_out) {
+        sched_out[0] = best.windowed;
+        sched_out[1] = best.window_kb;
+        sched_out[2] = best.max_passes;
+        sched_out[3] = best.lpr;
+        sched_out[4] = best.blocks_per_cu;
+        sched_out[5] = int(best_us);
+    }
+    return HPHI_OK;
+}

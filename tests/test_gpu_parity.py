@@ -375,3 +375,51 @@ def test_tpq_trajectory_matches_oracle(dtype, tol):
         assert np.allclose(us[:, 0, bb], u_ref, rtol=0, atol=tol)
         assert np.allclose(us[:, 1, bb], h2_ref, rtol=0, atol=tol)
         assert np.allclose(us[:, 2, bb], osv.tpq_beta(u_ref, ns, l), rtol=0, atol=100 * tol)
+
+
+@pytest.mark.parametrize("window_kb,nvec", [(1, 1), (2, 4), (8, 16)])
+def test_hv_windowed_multipass(monkeypatch, window_kb, nvec):
+    """Small L2 windows force several passes (operators split by flip bits, bit-permuted row order)."""
+    monkeypatch.setenv("HPHI_L2_WINDOW_KB", str(window_kb))
+    desc = BasisDesc("spin", 12)
+    terms = kh_honeycomb_terms(lx=3, ly=2, random_dirs=True, seed=9) + \
+        L.random_spin_terms(12, 6, 9, conserve_sz=False, fields=True, real=True)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(60, 60 + nvec)), True)
+    for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 3e-6)):
+        vd = _to_dev(v, dt)
+        if nvec == 1:
+            vd = vd.reshape(-1)
+        red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+        u = hp.hphi_hv(ham, vd, a=0.5, b=-0.25, reduce=red).cpu().numpy().astype(np.complex128)
+        u = u.reshape(len(st), nvec)
+        vin = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+        H = oh.sparse_h(desc, terms, st)
+        hx = H @ vin
+        ref = 0.5 * hx - 0.25 * vin
+        assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
+        red = red.cpu().numpy().reshape(4, nvec)
+        for bb in range(nvec):
+            assert abs(red[1, bb] - np.vdot(vin[:, bb], hx[:, bb]).real) <= 10 * tol * np.linalg.norm(hx[:, bb]) * np.linalg.norm(vin[:, bb])
+
+
+@pytest.mark.parametrize("nvec,dt", [(16, torch.complex64), (1, torch.complex128)])
+def test_autotuned_schedule_keeps_parity(nvec, dt):
+    desc = BasisDesc("spin", 12)
+    terms = kh_honeycomb_terms(lx=3, ly=2, random_dirs=True, seed=5)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(80, 80 + nvec)), True)
+    vd = _to_dev(v, dt)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    sched = hp.hphi_hv_tune(ham, vd)
+    assert sched["windowed"] in (0, 1) and sched["max_passes"] >= 1 and sched["us"] >= 0
+    u = hp.hphi_hv(ham, vd).cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    vin = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    ref = oh.sparse_h(desc, terms, st) @ vin
+    tol = 1e-12 if dt == torch.complex128 else 3e-6
+    assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
