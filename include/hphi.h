@@ -180,6 +180,11 @@ typedef struct {
  * row sum and reduction is FP64 with FP64 coefficients, and results are
  * rounded once when stored (a multi-pass schedule also rounds the partial
  * sums it passes between passes).  opts NULL = {1, 0, NULL, NULL}.
+ * Workspace lives with the ham: reduction partials, and for a staged
+ * multi-pass schedule one or two device buffers of dim*nvec elements
+ * (copies of v in a later pass's row order), allocated on first use and
+ * kept until hphi_ham_free.  Calls that share a ham must therefore not run
+ * concurrently on different streams.
  * Returns HPHI_EDTYPE for a complex Hamiltonian with a real dtype. */
 int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
             const hphi_hv_opts* opts, void* stream);
@@ -187,13 +192,15 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
 /* Autotuner of the product's launch schedule.  Times candidate schedules of
  * hphi_hv on the caller's buffers (v: input, u: scratch output of the same
  * size, overwritten) -- for full-space bases of 6..32 bits the windowed
- * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes, or
- * a single natural-order pass; lanes per row (nvec >= 8); resident blocks
+ * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes,
+ * gathering from v itself or from staged copies of v in each pass's row
+ * order, or a single natural-order pass; lanes per row (nvec >= 8); resident blocks
  * per CU -- and pins the fastest for this (ham, nvec, dtype): later
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different
  * schedule may change the last bits of the reductions.  sched_out (host,
- * may be NULL) receives 6 ints: windowed, window_kb, max_passes,
+ * may be NULL) receives 6 ints: windowed (0: single pass, 1: windowed,
+ * 2: windowed with staged copies), window_kb, max_passes,
  * lanes_per_row, blocks_per_cu, microseconds per product call.  If the
  * environment variable HPHI_TUNE_CACHE names a file, the choice is
  * appended there and reused by later processes for the same device,

@@ -19,6 +19,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxGrid = 4096;           // blocks of the persistent H.v grid
 constexpr int kMaxNvec = 16;
 constexpr int kNQ = 4;                   // reduced quantities per vector
+constexpr int kMaxPassOps = 1024;        // operators per windowed pass (LDS pattern table <= 128 KB)
 
 // One packed operator of the on-the-fly product (Sec. 3.3).
 //
@@ -42,7 +43,11 @@ struct DevOp {
 // Launch schedule of the product kernels (chosen by hphi_hv_tune or by
 // defaults).  Zero fields mean "default".
 struct Schedule {
-    int windowed = 1;       // windowed full-space kernel when it applies
+    // 0: single-pass product kernel; 1: windowed full-space kernel when it
+    // applies; 2: windowed, and every pass after the first gathers from a
+    // copy of v stored in that pass's processing order (written by the
+    // previous pass), so its window is one contiguous block of memory
+    int windowed = 1;
     int window_kb = 2048;   // L2 budget per XCD for a window block
     int max_passes = 3;     // passes of the windowed kernel (1 = natural order)
     int lpr = 0;            // lanes per row (nvec >= 8); 0 = default
@@ -83,6 +88,11 @@ struct PassPlan {
     // compact operators, each pass padded to a multiple of 4 entries
     std::vector<int32_t> kop_begin; // [n_pass + 1]
     KOp<double>* d_kop64 = nullptr;
+    // staged variant: the same records with the flip mask of every pass
+    // after the first expressed in that pass's processing-index bits
+    KOp<double>* d_kopq = nullptr;
+    std::vector<int32_t> inv;       // [n_pass][64]: configuration bit -> processing-index bit
+    int32_t* d_inv = nullptr;
 };
 
 // Device view of a basis, passed by value to kernels.
@@ -130,7 +140,9 @@ struct hphi_ham {
     int grid = 0;                 // persistent grid of the product kernels
     double* d_partials = nullptr; // [kMaxGrid][kNQ * kMaxNvec]
     double* d_red = nullptr;      // [kNQ * kMaxNvec]
-    std::mutex plan_mu;           // guards the lazily built pass plans and tuned schedules
+    std::mutex plan_mu;           // guards the lazily built pass plans, staging buffers and tuned schedules
+    void* d_stage[2] = {nullptr, nullptr};   // copies of v in a later pass's order (staged schedule)
+    size_t stage_bytes[2] = {0, 0};
     std::vector<hphi::PassPlan*> plans;
     struct Tuned {
         int nvec, dtype;
@@ -199,6 +211,9 @@ int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const
 
 // pass plan of the windowed product (plan.cpp); nullptr if not applicable
 const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes);
+// staging buffers of at least `bytes` each (grown on demand, kept with the
+// Hamiltonian); returns nonzero if they cannot be had
+int get_stage_buffers(const hphi_ham* ham, size_t bytes, int count, void** out);
 
 // host tridiagonal eigensolver (tridiag.cpp)
 double tridiag_lowest(const double* alpha, const double* beta, int n, double* evec);

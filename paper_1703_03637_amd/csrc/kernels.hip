@@ -1,6 +1,7 @@
 // gfx950 kernels of the matrix-free product and its reductions.
 //
-// Product (Sec. 3.3): each lane owns one row s of the output ("pull").  For
+// Product (Sec. 3.3): each row s of the output is owned by one lane, or by
+// LPR = 2, 4 or 8 lanes that split its vectors when nvec >= 8 ("pull").  For
 // every packed operator it reads the two bits that select the pattern p,
 // adds the diagonal part d[p], and, if the pulled element <s|H|s^mask> is
 // nonzero, forms the target t = s ^ mask, applies the fermion sign
@@ -76,51 +77,87 @@ __device__ __forceinline__ uint64_t unrank_row(const BasisDev& b, int64_t row) {
     return (b.h_val[k] << b.b_lo) | uint64_t(b.lows[b.h_lobase[k] + (row - b.h_row[k])]);
 }
 
-// ---- row loads/stores of NE scalars (vectorised by size)
-template <typename S, int NE>
-__device__ __forceinline__ void load_row(const S* __restrict__ base, int64_t idx, S (&out)[NE]) {
-    constexpr int BYTES = NE * int(sizeof(S));
-    const char* p = reinterpret_cast<const char*>(base) + idx * BYTES;
-    if constexpr (BYTES % 16 == 0) {
-#pragma unroll
-        for (int k = 0; k < BYTES / 16; ++k) {
-            const uint4 w = reinterpret_cast<const uint4*>(p)[k];
-            __builtin_memcpy(reinterpret_cast<char*>(out) + 16 * k, &w, 16);
-        }
-    } else if constexpr (BYTES % 8 == 0) {
-#pragma unroll
-        for (int k = 0; k < BYTES / 8; ++k) {
-            const uint2 w = reinterpret_cast<const uint2*>(p)[k];
-            __builtin_memcpy(reinterpret_cast<char*>(out) + 8 * k, &w, 8);
-        }
+// ---- lane share of an interleaved row.  A row of nvec vectors is split
+// over LPR lanes in chunks of CB = min(16, lane bytes) bytes, dealt
+// round-robin: lane `sub` owns chunks sub, sub + LPR, sub + 2 LPR, ...  One
+// 16-byte load instruction of the LPR lanes of a row therefore reads
+// LPR * 16 contiguous bytes of it (a whole 128-byte line at LPR = 8), so
+// no line is requested by several instructions.
+template <typename S, int NE, int LPR>
+struct LaneLayout {
+    static constexpr int LB = NE * int(sizeof(S));     // bytes per lane per row
+    static constexpr int CB = LB >= 16 ? 16 : LB;      // chunk bytes
+    static constexpr int NCH = LB / CB;                // chunks per lane
+    static constexpr int CPS = CB / int(sizeof(S));    // scalars per chunk
+    static constexpr int RB = LB * LPR;                // row bytes
+};
+
+template <int CB>
+__device__ __forceinline__ void copy_chunk(char* dst, const char* src) {
+    if constexpr (CB == 16) {
+        const uint4 w = *reinterpret_cast<const uint4*>(src);
+        __builtin_memcpy(dst, &w, 16);
+    } else if constexpr (CB == 8) {
+        const uint2 w = *reinterpret_cast<const uint2*>(src);
+        __builtin_memcpy(dst, &w, 8);
     } else {
-#pragma unroll
-        for (int k = 0; k < NE; ++k) out[k] = reinterpret_cast<const S*>(p)[k];
+        static_assert(CB == 4, "chunk of 4, 8 or 16 bytes");
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(src);
+        __builtin_memcpy(dst, &w, 4);
     }
 }
 
-template <typename S, int NE>
-__device__ __forceinline__ void store_row(S* __restrict__ base, int64_t idx, const S (&in)[NE]) {
-    constexpr int BYTES = NE * int(sizeof(S));
-    char* p = reinterpret_cast<char*>(base) + idx * BYTES;
-    if constexpr (BYTES % 16 == 0) {
-#pragma unroll
-        for (int k = 0; k < BYTES / 16; ++k) {
-            uint4 w;
-            __builtin_memcpy(&w, reinterpret_cast<const char*>(in) + 16 * k, 16);
-            reinterpret_cast<uint4*>(p)[k] = w;
-        }
-    } else if constexpr (BYTES % 8 == 0) {
-#pragma unroll
-        for (int k = 0; k < BYTES / 8; ++k) {
-            uint2 w;
-            __builtin_memcpy(&w, reinterpret_cast<const char*>(in) + 8 * k, 8);
-            reinterpret_cast<uint2*>(p)[k] = w;
-        }
+template <int CB>
+__device__ __forceinline__ void put_chunk(char* dst, const char* src) {
+    if constexpr (CB == 16) {
+        uint4 w;
+        __builtin_memcpy(&w, src, 16);
+        *reinterpret_cast<uint4*>(dst) = w;
+    } else if constexpr (CB == 8) {
+        uint2 w;
+        __builtin_memcpy(&w, src, 8);
+        *reinterpret_cast<uint2*>(dst) = w;
     } else {
-#pragma unroll
-        for (int k = 0; k < NE; ++k) reinterpret_cast<S*>(p)[k] = in[k];
+        uint32_t w;
+        __builtin_memcpy(&w, src, 4);
+        *reinterpret_cast<uint32_t*>(dst) = w;
     }
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void load_lane(const S* __restrict__ base, int64_t row, int sub, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    const char* p = reinterpret_cast<const char*>(base) + row * Ly::RB + sub * Ly::CB;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, p + j * LPR * Ly::CB);
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void store_lane(S* __restrict__ base, int64_t row, int sub, const S (&in)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    char* p = reinterpret_cast<char*>(base) + row * Ly::RB + sub * Ly::CB;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        put_chunk<Ly::CB>(p + j * LPR * Ly::CB, reinterpret_cast<const char*>(in) + j * Ly::CB);
+}
+
+// vector index of the lane's b-th vector (b < NE / NC)
+template <typename S, int NE, int LPR, int NC>
+__device__ __forceinline__ int lane_vec(int sub, int b) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    const int e = NC * b;
+    return ((e / Ly::CPS * LPR + sub) * Ly::CPS + e % Ly::CPS) / NC;
+}
+
+// inverse: lane share `sub` and local index `bi` of vector g
+template <typename S, int NE, int LPR, int NC>
+__host__ __device__ constexpr void vec_lane(int g, int& sub, int& bi) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    const int eg = NC * g;
+    const int c = eg / Ly::CPS;
+    sub = c % LPR;
+    bi = ((c / LPR) * Ly::CPS + eg % Ly::CPS) / NC;
 }
 
 struct HvArgs {
@@ -170,7 +207,8 @@ __device__ __forceinline__ uint32_t parity_masked(typename StateT<W64>::type s, 
 
 // Reduce one quantity over the rows held by a wavefront.  Each lane holds
 // VPL per-row values (its share of the vectors); afterwards lane L holds the
-// wave sum for vector (L & (LPR-1)) * VPL + (L >> (6 - log2 VPL)).  The
+// wave sum for the local vector L >> (6 - log2 VPL) of share L & (LPR-1)
+// (vec_lane maps a vector to its share and local index).  The
 // first log2(VPL) exchange steps run in the storage precision (at most VPL
 // <= 16 products summed), the remaining steps and everything after in FP64.
 // branch-free choice between two values by a lane mask (all ones / zero):
@@ -243,7 +281,8 @@ __device__ __forceinline__ void wave_reduce_quantities(const double (&x)[NE], co
 
 // S: storage scalar, CPLX: complex vectors, CCOEF: complex coefficients,
 // SECTOR: split-table rank, B: interleaved vectors per row, LPR: lanes per
-// row (each lane owns B/LPR of the vectors), W64: configurations above 32 bits.
+// row (each lane owns B/LPR of the vectors, in interleaved chunks),
+// W64: configurations above 32 bits.
 template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
 __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     using ST = typename StateT<W64>::type;
@@ -268,15 +307,13 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     const ConstOp* ops = (const ConstOp*)(A.ops);
     const BasisDev& bs = A.bs;
     const int n_ops = A.n_ops;
-    // element offset of this lane's share inside a row
-    const int64_t lane_off = int64_t(sub) * NE;
-
     // all arithmetic in FP64: FP32 types are a storage format only
     double sx[VPL], cy[VPL];
 #pragma unroll
     for (int b = 0; b < VPL; ++b) {
-        sx[b] = A.sx ? A.sx[sub * VPL + b] : 1.0;
-        cy[b] = (A.y && A.cy) ? A.cy[sub * VPL + b] : 0.0;
+        const int gv = lane_vec<S, NE, LPR, NC>(sub, b);
+        sx[b] = A.sx ? A.sx[gv] : 1.0;
+        cy[b] = (A.y && A.cy) ? A.cy[gv] : 0.0;
     }
     const double ca = A.a, cb = A.b;
 
@@ -350,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
                         }
                         const int64_t idx = rank_of<SECTOR>(bs, uint64_t(t));
                         alignas(16) S g[NE];
-                        load_row<S, NE>(v + lane_off, idx * LPR, g);
+                        load_lane<S, NE, LPR>(v, idx, sub, g);
 #pragma unroll
                         for (int b = 0; b < VPL; ++b) {
                             if constexpr (CPLX) {
@@ -374,10 +411,10 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
             double xr[NE], ur[NE];
             if (valid) {
                 alignas(16) S vr[NE];
-                load_row<S, NE>(v + lane_off, row * LPR, vr);
+                load_lane<S, NE, LPR>(v, row, sub, vr);
                 if (y) {
                     alignas(16) S yr[NE];
-                    load_row<S, NE>(y + lane_off, row * LPR, yr);
+                    load_lane<S, NE, LPR>(y, row, sub, yr);
 #pragma unroll
                     for (int b = 0; b < VPL; ++b)
 #pragma unroll
@@ -402,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
                     alignas(16) S us[NE];
 #pragma unroll
                     for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
-                    store_row<S, NE>(u + lane_off, row * LPR, us);
+                    store_lane<S, NE, LPR>(u, row, sub, us);
                 }
             } else {
 #pragma unroll
@@ -423,7 +460,8 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     __syncthreads();
     if (int(threadIdx.x) < kNQ * B) {
         const int k = threadIdx.x / B, b = threadIdx.x % B;
-        const int bsub = b / VPL, bi = b % VPL;
+        int bsub = 0, bi = 0;
+        vec_lane<S, NE, LPR, NC>(b, bsub, bi);
         const int L = (bi << (6 - LOGV)) | bsub;
         double acc = 0.0;
 #pragma unroll
@@ -442,6 +480,15 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
 // of rows currently in flight.  mode bit 0: first pass (no partial sum to
 // read); bit 1: last pass (epilogue and reductions).  Partial sums of H v
 // (unscaled) travel through u between passes.
+//
+// Staged schedule: the configuration bits of a later pass's window are in
+// general scattered over the row index, so its window rows lie far apart
+// in memory and compete for a few L2 sets.  There, the previous pass also
+// writes each row of v it visits to `stage` at the row's processing index
+// in the next pass (inv_next maps configuration bits to those index bits),
+// and the next pass gathers from that copy at q ^ xmask', where xmask' is
+// the flip mask in processing-index bits: its window is then one
+// contiguous block.
 struct HvwArgs {
     const void* kops;    // KOp<S> records of this pass, a multiple of 4
     int kop_begin;
@@ -450,7 +497,10 @@ struct HvwArgs {
     int nbits;
     int mode;
     int64_t n_tiles;
-    const void* v;
+    const void* v;       // gather source: v (row index s) or a staged copy (index q)
+    int g_q;             // 1: v is a staged copy indexed by the processing index
+    void* stage;         // nullptr, or the staged copy of v for the next pass
+    const int32_t* inv_next;   // [64] configuration bit -> next pass's index bit
     void* u;
     const void* y;
     const double* cy;
@@ -459,6 +509,9 @@ struct HvwArgs {
     const int* stop;
     double* partials;
 };
+
+// per-block pattern table of the windowed product (dynamic LDS)
+extern __shared__ double lds_tab[];
 
 template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
 __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
@@ -483,7 +536,13 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     const ConstKOp* kops = (const ConstKOp*)(A.kops);
     typedef const __attribute__((address_space(4))) int32_t ConstI32;
     const ConstI32* perm = (const ConstI32*)(A.perm);
-    const int64_t lane_off = int64_t(sub) * NE;
+    const ConstI32* inv_next = (const ConstI32*)(A.inv_next);
+    S* __restrict__ stg = static_cast<S*>(A.stage);
+    const bool gq = A.g_q != 0;
+    // next-pass index bit of each of the six in-tile index bits
+    uint32_t nlm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) nlm[k] = stg ? (1u << inv_next[perm[k]]) : 0u;
 
     const int xcd = blockIdx.x & 7;
     const int waves_x = int(gridDim.x >> 3) * kWavesPerBlock;
@@ -495,45 +554,81 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
 
     double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
 
+    // pattern table of this pass's operators in LDS: entry (o, p) holds
+    // {c[p], d[p]} (real coefficients) or {c[p], ci[p], d[p], 0}; each lane
+    // reads the entry of its own row pattern p (at most four distinct
+    // addresses per operator across the wavefront)
+    constexpr int TE = CCOEF ? 4 : 2;
+    const int n_ops = A.kop_end - A.kop_begin;
+    for (int i = int(threadIdx.x); i < n_ops * 4; i += kBlock) {
+        const ConstKOp& rec = kops[A.kop_begin + (i >> 2)];
+        const int q = i & 3;
+        const double c0 = rec.c[0], c1 = rec.c[1], c2 = rec.c[2], c3 = rec.c[3];
+        const double d0 = rec.d[0], d1 = rec.d[1], d2 = rec.d[2], d3 = rec.d[3];
+        lds_tab[i * TE] = sel4(q, c0, c1, c2, c3);
+        if constexpr (CCOEF) {
+            const double e0 = rec.ci[0], e1 = rec.ci[1], e2 = rec.ci[2], e3 = rec.ci[3];
+            lds_tab[i * TE + 1] = sel4(q, e0, e1, e2, e3);
+            lds_tab[i * TE + 2] = sel4(q, d0, d1, d2, d3);
+            lds_tab[i * TE + 3] = 0.0;
+        } else {
+            lds_tab[i * TE + 1] = sel4(q, d0, d1, d2, d3);
+        }
+    }
+    __syncthreads();
+
+    // gathered rows stay live across operators: a lane whose element is zero
+    // skips its load and multiplies the previous (finite) values by 0.0
+    alignas(16) S g[4][NE];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) g[k][e] = S(0);
+
     for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
-        // configuration bits of the tile index (uniform)
-        uint32_t s_tile = 0;
+        // configuration bits of the tile index, and their next-pass index bits (uniform)
+        uint32_t s_tile = 0, qn_tile = 0;
         for (int k = 6; k < A.nbits; ++k)
-            if ((tile >> (k - 6)) & 1) s_tile |= 1u << perm[k];
+            if ((tile >> (k - 6)) & 1) {
+                const int c = perm[k];
+                s_tile |= 1u << c;
+                if (stg) qn_tile |= 1u << inv_next[c];
+            }
 #pragma unroll 1
         for (int pass = 0; pass < LPR; ++pass) {
             const int r = pass * RPW + rlane;      // position within the 64-row tile
-            uint32_t s = s_tile;
+            uint32_t s = s_tile, qn = qn_tile;
 #pragma unroll
             for (int k = 0; k < 6; ++k)
-                if ((r >> k) & 1) s |= 1u << perm[k];
+                if ((r >> k) & 1) {
+                    s |= 1u << perm[k];
+                    qn |= nlm[k];
+                }
             const int64_t row = int64_t(s);
+            // index of this row in the gather source
+            const uint32_t base = gq ? ((uint32_t(tile) << 6) | uint32_t(r)) : s;
 
             double acc[NE];
 #pragma unroll
             for (int e = 0; e < NE; ++e) acc[e] = 0.0;
             double dsum = 0.0;
-            // operators in groups of 4: read the records, decode all, issue
-            // every gather, then accumulate (FP64 coefficients and sums)
-            for (int o = A.kop_begin; o < A.kop_end; o += 4) {
+            // operators in groups of 4: decode all, issue every gather, then
+            // accumulate (FP64 coefficients and sums)
+            for (int o = 0; o < n_ops; o += 4) {
                 double crk[4], cik[4];
                 uint32_t tk[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const ConstKOp& rec = kops[o + k];
+                    const ConstKOp& rec = kops[A.kop_begin + o + k];
                     const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj;
-                    const double rd0 = rec.d[0], rd1 = rec.d[1], rd2 = rec.d[2], rd3 = rec.d[3];
-                    const double rc0 = rec.c[0], rc1 = rec.c[1], rc2 = rec.c[2], rc3 = rec.c[3];
-                    const uint32_t b0 = __builtin_amdgcn_ubfe(s, bi, 1u);
-                    const uint32_t b1 = __builtin_amdgcn_ubfe(s, bj, 1u);
-                    const double d01 = b0 ? rd1 : rd0, d23 = b0 ? rd3 : rd2;
-                    dsum += b1 ? d23 : d01;
-                    const double c01 = b0 ? rc1 : rc0, c23 = b0 ? rc3 : rc2;
-                    double cr = b1 ? c23 : c01, ci = 0.0;
+                    const uint32_t pat = __builtin_amdgcn_ubfe(s, bi, 1u) | (__builtin_amdgcn_ubfe(s, bj, 1u) << 1);
+                    const double* te = lds_tab + ((o + k) * 4 + int(pat)) * TE;
+                    double cr = te[0], ci = 0.0;
                     if constexpr (CCOEF) {
-                        const double ri0 = rec.ci[0], ri1 = rec.ci[1], ri2 = rec.ci[2], ri3 = rec.ci[3];
-                        const double e01 = b0 ? ri1 : ri0, e23 = b0 ? ri3 : ri2;
-                        ci = b1 ? e23 : e01;
+                        ci = te[1];
+                        dsum += te[2];
+                    } else {
+                        dsum += te[1];
                     }
                     if (sm != 0) {
                         const bool neg = (__popc(s & sm) & 1) != 0;
@@ -542,18 +637,12 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                     }
                     crk[k] = cr;
                     cik[k] = ci;
-                    tk[k] = s ^ xm;
+                    tk[k] = base ^ xm;
                 }
-                alignas(16) S g[4][NE];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
-                    if (act) {
-                        load_row<S, NE>(v + lane_off, int64_t(tk[k]) * LPR, g[k]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < NE; ++e) g[k][e] = S(0);
-                    }
+                    if (act) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -577,12 +666,13 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             }
 
             alignas(16) S vr[NE];
-            load_row<S, NE>(v + lane_off, row * LPR, vr);
+            load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
+            if (stg) store_lane<S, NE, LPR>(stg, int64_t(qn), sub, vr);
 #pragma unroll
             for (int e = 0; e < NE; ++e) acc[e] += dsum * double(vr[e]);   // raw (unscaled) H v of this pass
             if (!first) {
                 alignas(16) S pr[NE];
-                load_row<S, NE>(u + lane_off, row * LPR, pr);
+                load_lane<S, NE, LPR>(u, row, sub, pr);
 #pragma unroll
                 for (int e = 0; e < NE; ++e) acc[e] += double(pr[e]);
             }
@@ -590,16 +680,16 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 alignas(16) S ps[NE];
 #pragma unroll
                 for (int e = 0; e < NE; ++e) ps[e] = S(acc[e]);
-                store_row<S, NE>(u + lane_off, row * LPR, ps);
+                store_lane<S, NE, LPR>(u, row, sub, ps);
                 continue;
             }
             double ur[NE], xr[NE];
             if (y) {
                 alignas(16) S yr[NE];
-                load_row<S, NE>(y + lane_off, row * LPR, yr);
+                load_lane<S, NE, LPR>(y, row, sub, yr);
 #pragma unroll
                 for (int b = 0; b < VPL; ++b) {
-                    const double c = A.cy ? A.cy[sub * VPL + b] : 0.0;
+                    const double c = A.cy ? A.cy[lane_vec<S, NE, LPR, NC>(sub, b)] : 0.0;
 #pragma unroll
                     for (int c2 = 0; c2 < NC; ++c2) ur[NC * b + c2] = c * double(yr[NC * b + c2]);
                 }
@@ -610,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             const double ca = A.a, cb = A.b;
 #pragma unroll
             for (int b = 0; b < VPL; ++b) {
-                const double sc = A.sx ? A.sx[sub * VPL + b] : 1.0;
+                const double sc = A.sx ? A.sx[lane_vec<S, NE, LPR, NC>(sub, b)] : 1.0;
 #pragma unroll
                 for (int c2 = 0; c2 < NC; ++c2) {
                     const int e = NC * b + c2;
@@ -625,7 +715,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 alignas(16) S us[NE];
 #pragma unroll
                 for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
-                store_row<S, NE>(u + lane_off, row * LPR, us);
+                store_lane<S, NE, LPR>(u, row, sub, us);
             }
             wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
         }
@@ -637,7 +727,8 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     __syncthreads();
     if (int(threadIdx.x) < kNQ * B) {
         const int k = threadIdx.x / B, b = threadIdx.x % B;
-        const int bsub = b / VPL, bi = b % VPL;
+        int bsub = 0, bi = 0;
+        vec_lane<S, NE, LPR, NC>(b, bsub, bi);
         const int L = (bi << (6 - LOGV)) | bsub;
         double acc = 0.0;
 #pragma unroll
@@ -941,6 +1032,7 @@ static int launch_hv_l(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
         switch (sc.lpr) {
             case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, false>(L, sc, st);
             case 4: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false>(L, sc, st);
+            case 8: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 8, false>(L, sc, st);
         }
     }
     return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, false>(L, sc, st);
@@ -960,7 +1052,8 @@ static int launch_hv_b(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
 
 // ---- windowed full-space launches
 template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
-static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, hipStream_t st) {
+static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
+                        hipStream_t st) {
     const hphi_ham* H = L.ham;
     static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR>);
     const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
@@ -976,13 +1069,21 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
+    if (P->n_pass > 1 && !L.u) return set_error(HPHI_EINVAL, "multi-pass product needs an output buffer");
+    if (staged && !stage[0]) return set_error(HPHI_EINVAL, "staged product without staging buffers");
     for (int p = 0; p < P->n_pass; ++p) {
-        A.kops = P->d_kop64;
+        const bool next = staged && p + 1 < P->n_pass;
+        A.kops = staged ? P->d_kopq : P->d_kop64;
         A.kop_begin = P->kop_begin[p];
         A.kop_end = P->kop_begin[p + 1];
         A.perm = P->d_perm + size_t(p) * 64;
         A.mode = (p == 0 ? 1 : 0) | (p == P->n_pass - 1 ? 2 : 0);
-        hvw_kernel<S, CPLX, CCOEF, B, LPR><<<grid, kBlock, 0, st>>>(A);
+        A.v = (staged && p > 0) ? stage[(p - 1) & 1] : L.v;
+        A.g_q = (staged && p > 0) ? 1 : 0;
+        A.stage = next ? stage[p & 1] : nullptr;
+        A.inv_next = next ? P->d_inv + size_t(p + 1) * 64 : nullptr;
+        const size_t lds = size_t(A.kop_end - A.kop_begin) * 4 * (CCOEF ? 4 : 2) * sizeof(double);
+        hvw_kernel<S, CPLX, CCOEF, B, LPR><<<grid, kBlock, lds, st>>>(A);
         int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
         if (rc) return rc;
     }
@@ -994,14 +1095,16 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
 }
 
 template <typename S, bool CPLX, bool CCOEF, int B>
-static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc, hipStream_t st) {
+static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
+                        hipStream_t st) {
     if constexpr (B >= 8) {
         switch (sc.lpr) {
-            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2>(L, P, sc, st);
-            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4>(L, P, sc, st);
+            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2>(L, P, sc, staged, stage, st);
+            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4>(L, P, sc, staged, stage, st);
+            case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8>(L, P, sc, staged, stage, st);
         }
     }
-    return launch_hvw_t<S, CPLX, CCOEF, B, 1>(L, P, sc, st);
+    return launch_hvw_t<S, CPLX, CCOEF, B, 1>(L, P, sc, staged, stage, st);
 }
 
 // windowed product when it applies (full space, <= 32 bits, no in-place
@@ -1013,13 +1116,31 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     const int row_bytes = L.nvec * int(sizeof(S)) * (CPLX ? 2 : 1);
     const PassPlan* P = get_plan(L.ham, row_bytes, sc.window_kb, sc.max_passes);
     if (!P) return 1;
-    if (L.y && P->n_pass > 1) return 1;
+    // several passes carry partial sums through u: they need a real output
+    // buffer that is not also an input
+    if (P->n_pass > 1 && (!L.u || L.y)) return 1;
+    // the pattern table of a pass lives in LDS: at most kMaxPassOps operators
+    for (int p = 0; p < P->n_pass; ++p)
+        if (P->kop_begin[p + 1] - P->kop_begin[p] > kMaxPassOps) return 1;
+    bool staged = sc.windowed == 2 && P->n_pass > 1;
+    void* stage[2] = {nullptr, nullptr};
+    if (staged) {
+        // staging buffers are allocated on first use; never inside a graph capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(st, &cs);
+        const size_t bytes = size_t(Bs->dim) * size_t(row_bytes);
+        const int count = P->n_pass > 2 ? 2 : 1;
+        bool have = true;
+        for (int i = 0; i < count; ++i) have = have && L.ham->stage_bytes[i] >= bytes;
+        if ((cs != hipStreamCaptureStatusNone && !have) || get_stage_buffers(L.ham, bytes, count, stage))
+            staged = false;
+    }
     switch (L.nvec) {
-        case 1: return launch_hvw_b<S, CPLX, CCOEF, 1>(L, P, sc, st);
-        case 2: return launch_hvw_b<S, CPLX, CCOEF, 2>(L, P, sc, st);
-        case 4: return launch_hvw_b<S, CPLX, CCOEF, 4>(L, P, sc, st);
-        case 8: return launch_hvw_b<S, CPLX, CCOEF, 8>(L, P, sc, st);
-        case 16: return launch_hvw_b<S, CPLX, CCOEF, 16>(L, P, sc, st);
+        case 1: return launch_hvw_b<S, CPLX, CCOEF, 1>(L, P, sc, staged, stage, st);
+        case 2: return launch_hvw_b<S, CPLX, CCOEF, 2>(L, P, sc, staged, stage, st);
+        case 4: return launch_hvw_b<S, CPLX, CCOEF, 4>(L, P, sc, staged, stage, st);
+        case 8: return launch_hvw_b<S, CPLX, CCOEF, 8>(L, P, sc, staged, stage, st);
+        case 16: return launch_hvw_b<S, CPLX, CCOEF, 16>(L, P, sc, staged, stage, st);
     }
     return 1;
 }

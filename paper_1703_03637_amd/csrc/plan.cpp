@@ -180,14 +180,40 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
     }
     P->kop_begin[P->n_pass] = int(k64.size());
     if (k64.empty()) k64.push_back(KOp<double>{});
-    if (hipMalloc(&P->d_kop64, k64.size() * sizeof(KOp<double>)) != hipSuccess) {
+    // inverse permutations, and the flip masks of passes after the first in
+    // processing-index bits (a bit permutation commutes with XOR, so the
+    // partner of processing index q is q ^ perm^-1(xmask))
+    P->inv.assign(size_t(P->n_pass) * 64, 0);
+    for (int p = 0; p < P->n_pass; ++p)
+        for (int k = 0; k < nbits; ++k) P->inv[size_t(p) * 64 + P->perm[size_t(p) * 64 + k]] = k;
+    std::vector<KOp<double>> kq = k64;
+    for (int p = 1; p < P->n_pass; ++p)
+        for (int o = P->kop_begin[p]; o < P->kop_begin[p + 1]; ++o) {
+            uint32_t m = 0;
+            for (int b = 0; b < nbits; ++b)
+                if ((kq[o].xm >> b) & 1u) m |= 1u << P->inv[size_t(p) * 64 + b];
+            kq[o].xm = m;
+        }
+    const size_t kb = k64.size() * sizeof(KOp<double>);
+    if (hipMalloc(&P->d_kop64, kb) != hipSuccess) {
         delete P;
         return nullptr;
     }
-    (void)hipMemcpy(P->d_kop64, k64.data(), k64.size() * sizeof(KOp<double>), hipMemcpyHostToDevice);
+    if (hipMalloc(&P->d_kopq, kb) != hipSuccess || hipMalloc(&P->d_inv, P->inv.size() * 4) != hipSuccess) {
+        (void)hipFree(P->d_kop64);
+        if (P->d_kopq) (void)hipFree(P->d_kopq);
+        delete P;
+        return nullptr;
+    }
+    (void)hipMemcpy(P->d_kop64, k64.data(), kb, hipMemcpyHostToDevice);
+    (void)hipMemcpy(P->d_kopq, kq.data(), kb, hipMemcpyHostToDevice);
+    (void)hipMemcpy(P->d_inv, P->inv.data(), P->inv.size() * 4, hipMemcpyHostToDevice);
     const size_t ob = std::max<size_t>(1, sorted.size()) * sizeof(DevOp);
     if (hipMalloc(&P->d_ops, ob) != hipSuccess || hipMalloc(&P->d_perm, P->perm.size() * 4) != hipSuccess) {
         if (P->d_ops) (void)hipFree(P->d_ops);
+        (void)hipFree(P->d_kop64);
+        (void)hipFree(P->d_kopq);
+        (void)hipFree(P->d_inv);
         delete P;
         return nullptr;
     }
@@ -226,6 +252,25 @@ const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int 
     }
     H->plans.push_back(p);
     return p->n_pass > 0 ? p : nullptr;
+}
+
+int get_stage_buffers(const hphi_ham* ham, size_t bytes, int count, void** out) {
+    hphi_ham* H = const_cast<hphi_ham*>(ham);
+    std::lock_guard<std::mutex> lock(H->plan_mu);
+    for (int i = 0; i < count; ++i) {
+        if (H->stage_bytes[i] < bytes) {
+            if (H->d_stage[i]) (void)hipFree(H->d_stage[i]);
+            H->d_stage[i] = nullptr;
+            H->stage_bytes[i] = 0;
+            if (hipMalloc(&H->d_stage[i], bytes) != hipSuccess) {
+                H->d_stage[i] = nullptr;
+                return 1;
+            }
+            H->stage_bytes[i] = bytes;
+        }
+        out[i] = H->d_stage[i];
+    }
+    return 0;
 }
 
 }  // namespace hphi

@@ -3,8 +3,8 @@
 //
 // The tuner times candidate schedules of the real product on the caller's
 // buffers -- window budget and number of passes of the windowed full-space
-// kernel (or the single-pass kernel), lanes per row, resident blocks per
-// CU -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
+// kernel with or without staged copies (or the single-pass kernel), lanes
+// per row, resident blocks per CU -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
 // HPHI_TUNE_CACHE set, choices are appended to that file, keyed by a
 // signature of the device, the space and the packed operators, and are
 // reused by later processes without timing.
@@ -36,7 +36,7 @@ Schedule default_schedule(int nvec) {
     s.window_kb = env_int("HPHI_L2_WINDOW_KB", s.window_kb);
     s.max_passes = env_int("HPHI_PASSES", s.max_passes);
     const int l = env_int("HPHI_LPR", 0);
-    if (nvec >= 8 && (l == 1 || l == 2 || l == 4)) s.lpr = l;
+    if (nvec >= 8 && (l == 1 || l == 2 || l == 4 || l == 8)) s.lpr = l;
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
     if (s.window_kb < 1) s.window_kb = 2048;
     if (s.max_passes < 1) s.max_passes = 1;
@@ -130,7 +130,7 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
 
     std::vector<Schedule> cands;
     std::vector<int> lprs = {1};
-    if (nvec >= 8) lprs = {1, 2, 4};
+    if (nvec >= 8) lprs = {1, 2, 4, 8};
     for (int bpc : {0, 4}) {
         for (int lpr : lprs) {
             Schedule s;
@@ -144,11 +144,13 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
             s.windowed = 1;
             cands.push_back(s);   // single natural pass, compact operators
             for (int wkb : {1024, 2048, 4096})
-                for (int mp : {2, 3}) {
-                    s.window_kb = wkb;
-                    s.max_passes = mp;
-                    cands.push_back(s);
-                }
+                for (int mp : {2, 3})
+                    for (int staged : {1, 2}) {
+                        s.windowed = staged;
+                        s.window_kb = wkb;
+                        s.max_passes = mp;
+                        cands.push_back(s);
+                    }
         }
     }
     hipEvent_t e0, e1;

@@ -377,10 +377,16 @@ def test_tpq_trajectory_matches_oracle(dtype, tol):
         assert np.allclose(us[:, 2, bb], osv.tpq_beta(u_ref, ns, l), rtol=0, atol=100 * tol)
 
 
-@pytest.mark.parametrize("window_kb,nvec", [(1, 1), (2, 4), (8, 16)])
-def test_hv_windowed_multipass(monkeypatch, window_kb, nvec):
-    """Small L2 windows force several passes (operators split by flip bits, bit-permuted row order)."""
+@pytest.mark.parametrize("staged", [1, 2])
+@pytest.mark.parametrize("window_kb,nvec,passes", [(1, 1, 3), (2, 4, 2), (8, 16, 3), (8, 16, 2)])
+def test_hv_windowed_multipass(monkeypatch, window_kb, nvec, passes, staged):
+    """Small L2 windows force several passes (operators split by flip bits, bit-permuted row order);
+    staged=2 makes every later pass gather from a copy of v written in its own row order."""
+    print(f"[gpu] windowed multipass window_kb={window_kb} nvec={nvec} passes={passes} staged={staged}",
+          flush=True)
     monkeypatch.setenv("HPHI_L2_WINDOW_KB", str(window_kb))
+    monkeypatch.setenv("HPHI_PASSES", str(passes))
+    monkeypatch.setenv("HPHI_WINDOWED", str(staged))
     desc = BasisDesc("spin", 12)
     terms = kh_honeycomb_terms(lx=3, ly=2, random_dirs=True, seed=9) + \
         L.random_spin_terms(12, 6, 9, conserve_sz=False, fields=True, real=True)
@@ -417,9 +423,78 @@ def test_autotuned_schedule_keeps_parity(nvec, dt):
     if nvec == 1:
         vd = vd.reshape(-1)
     sched = hp.hphi_hv_tune(ham, vd)
-    assert sched["windowed"] in (0, 1) and sched["max_passes"] >= 1 and sched["us"] >= 0
+    assert sched["windowed"] in (0, 1, 2) and sched["max_passes"] >= 1 and sched["us"] >= 0
     u = hp.hphi_hv(ham, vd).cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
     vin = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
     ref = oh.sparse_h(desc, terms, st) @ vin
     tol = 1e-12 if dt == torch.complex128 else 3e-6
     assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("window_kb", [1, 2048])
+def test_hv_reduce_only_with_multipass_schedule(monkeypatch, window_kb):
+    """Reduce-only calls (no output vector) must not take the multi-pass path, whatever the schedule."""
+    monkeypatch.setenv("HPHI_L2_WINDOW_KB", str(window_kb))
+    monkeypatch.setenv("HPHI_PASSES", "3")
+    desc = BasisDesc("spin", 12)
+    terms = kh_honeycomb_terms(lx=3, ly=2, random_dirs=True, seed=11)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), [90], True)[:, 0]
+    vd = _to_dev(v, torch.complex128)
+    red = torch.empty(4, dtype=torch.float64, device="cuda")
+    hp.hphi_hv(ham, vd, a=1.0, b=-0.5, reduce=red, write=False)
+    hx = oh.sparse_h(desc, terms, st) @ v
+    want = [np.vdot(v, v).real, np.vdot(v, hx).real, np.vdot(hx, hx).real,
+            np.linalg.norm(hx - 0.5 * v) ** 2]
+    assert np.allclose(red.cpu().numpy(), want, rtol=1e-12, atol=0)
+    # the written product (which may run several passes) gives the same sums
+    red3 = torch.empty(4, dtype=torch.float64, device="cuda")
+    u = hp.hphi_hv(ham, vd, a=1.0, b=-0.5, reduce=red3).cpu().numpy()
+    assert np.linalg.norm(u - (hx - 0.5 * v)) <= 1e-12 * np.linalg.norm(hx - 0.5 * v)
+    assert np.allclose(red3.cpu().numpy(), want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8])
+@pytest.mark.parametrize("case,windowed", [("spin_sz_dm", 0), ("kh_honeycomb12", 0), ("kh_honeycomb12", 1),
+                                           ("spin_full_real", 2)])
+@pytest.mark.parametrize("nvec", [8, 16])
+def test_hv_lanes_per_row(monkeypatch, lpr, case, windowed, nvec):
+    """Rows split over 1, 2, 4 or 8 lanes (interleaved 16-byte chunks): output, per-vector scales and
+    per-vector reductions all land on the right vector, for every storage type."""
+    print(f"[gpu] lanes per row lpr={lpr} case={case} windowed={windowed} nvec={nvec}", flush=True)
+    monkeypatch.setenv("HPHI_LPR", str(lpr))
+    monkeypatch.setenv("HPHI_WINDOWED", str(windowed))
+    if windowed:
+        monkeypatch.setenv("HPHI_L2_WINDOW_KB", "4")
+        monkeypatch.setenv("HPHI_PASSES", "2")
+    desc, terms, basis, ham = _case(case)
+    st = ob.states(desc)
+    H = oh.sparse_h(desc, terms, st)
+    dts = [(torch.complex128, 1e-12), (torch.complex64, 3e-6)]
+    if not ham.is_complex:
+        dts += [(torch.float64, 1e-12), (torch.float32, 3e-6)]
+    for dt, tol in dts:
+        cplx = dt in (torch.complex128, torch.complex64)
+        v = uniform_vectors(len(st), list(range(200, 200 + nvec)), cplx)
+        vd = _to_dev(v if cplx else v.real, dt)
+        vin = vd.cpu().numpy().astype(np.complex128)
+        scale = np.linspace(0.5, 2.0, nvec)
+        red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+        a, b = 0.75, -0.3
+        u = hp.hphi_hv(ham, vd, a=a, b=b, in_scale=torch.tensor(scale, device="cuda"), reduce=red)
+        u = u.cpu().numpy().astype(np.complex128)
+        x = vin * scale[None, :]
+        hx = H @ x
+        ref = a * hx + b * x
+        for k in range(nvec):
+            assert np.linalg.norm(u[:, k] - ref[:, k]) <= tol * np.linalg.norm(ref[:, k]), (dt, k)
+        red = red.cpu().numpy().reshape(4, nvec)
+        for k in range(nvec):
+            want = [np.vdot(x[:, k], x[:, k]).real, np.vdot(x[:, k], hx[:, k]).real,
+                    np.vdot(hx[:, k], hx[:, k]).real, np.vdot(ref[:, k], ref[:, k]).real]
+            scale_k = [abs(want[0]), np.linalg.norm(x[:, k]) * np.linalg.norm(hx[:, k]), abs(want[2]),
+                       abs(want[3])]
+            for q in range(4):
+                assert abs(red[q, k] - want[q]) <= 10 * tol * scale_k[q] + 1e-300, (dt, q, k)
