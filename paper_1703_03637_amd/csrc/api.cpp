@@ -220,6 +220,252 @@ int lz_run(const hphi_ham* H, int dtype, const void* v0, void* A, void* B, LzDev
     return HPHI_OK;
 }
 
+// ---- batched recurrence: several problems advance together, one launch
+// per kernel and step (uneven sizes share the persistent grid)
+
+struct LzBatch {
+    LzScalars* sc = nullptr;   // [n]
+    double* alpha = nullptr;   // [n][n_iter]
+    double* beta = nullptr;
+    double* evec = nullptr;
+    double* red = nullptr;     // [n][kNQ]
+    double* spart = nullptr;   // [kStreamGrid]
+    void* mem = nullptr;
+};
+
+int lzb_alloc(LzBatch& D, int n, int n_iter) {
+    const size_t sc_b = (size_t(n) * sizeof(LzScalars) + 255) / 256 * 256;
+    const size_t arr = size_t(n) * n_iter * 8;
+    const size_t bytes = sc_b + 3 * arr + size_t(n) * kNQ * 8 + size_t(kStreamGrid) * 8 + 1024;
+    char* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return set_error(HPHI_ENOMEM, "hphi_lanczos: batched workspace");
+    D.mem = p;
+    D.sc = (LzScalars*)p;
+    p += sc_b;
+    D.alpha = (double*)p;
+    p += arr;
+    D.beta = (double*)p;
+    p += arr;
+    D.evec = (double*)p;
+    p += arr;
+    D.red = (double*)p;
+    p += size_t(n) * kNQ * 8;
+    D.spart = (double*)p;
+    return HPHI_OK;
+}
+
+struct BatchPlans {
+    MultiPlan hv_first, hv[2];
+    UpdPlan upd[2];
+    void release() {
+        for (void* m : {hv_first.mem, hv[0].mem, hv[1].mem, upd[0].mem, upd[1].mem})
+            if (m) (void)hipFree(m);
+        hv_first.mem = hv[0].mem = hv[1].mem = upd[0].mem = upd[1].mem = nullptr;
+    }
+};
+
+// parity 0: X = A, Y = B; parity 1: X = B, Y = A
+int lzb_plans(const hphi_ham* const* H, int n, int dtype, void* const* A, void* const* Bv, LzBatch& D,
+              void* const* acc, BatchPlans& P) {
+    std::vector<HvLaunch> Ls(n);
+    std::vector<UpdDesc> U(n);
+    std::vector<double*> ured(n);
+    for (int first = 1; first >= 0; --first)
+        for (int q = 0; q < (first ? 1 : 2); ++q) {
+            for (int p = 0; p < n; ++p) {
+                void* X = q ? Bv[p] : A[p];
+                void* Y = q ? A[p] : Bv[p];
+                HvLaunch& L = Ls[p];
+                L = HvLaunch{};
+                L.ham = H[p];
+                L.v = X;
+                L.u = Y;
+                L.y = first ? nullptr : Y;
+                L.cy = &D.sc[p].cy;
+                L.sx = &D.sc[p].s_cur;
+                L.a = 1.0;
+                L.b = 0.0;
+                L.nvec = 1;
+                L.dtype = dtype;
+                L.stop = &D.sc[p].stop;
+                L.reduce_out = D.red + size_t(kNQ) * p;
+                if (!first) {
+                    UpdDesc& u = U[p];
+                    u = UpdDesc{};
+                    u.y = Y;
+                    u.x = X;
+                    u.n = H[p]->basis->dim * (dtype_complex(dtype) ? 2 : 1);
+                    u.c2 = &D.sc[p].c2;
+                    u.acc = acc ? static_cast<double*>(acc[p]) : nullptr;
+                    u.ec = &D.sc[p].ecoef;
+                    u.stop = &D.sc[p].stop;
+                    ured[p] = D.red + size_t(kNQ) * p;
+                }
+            }
+            int rc = hv_multi_prepare(Ls.data(), n, first ? &P.hv_first : &P.hv[q]);
+            if (!rc && !first) rc = upd_multi_prepare(U.data(), ured.data(), n, dtype, &P.upd[q]);
+            if (rc) return rc;
+        }
+    return HPHI_OK;
+}
+
+int lzb_iteration(const BatchPlans& P, int n, int parity, bool first, LzBatch& D, bool acc, int n_iter,
+                  hipStream_t st) {
+    int rc = hv_multi_launch(first ? P.hv_first : P.hv[parity], st);
+    if (!rc) rc = launch_lz_after_hv_multi(D.sc, D.red, D.alpha, acc ? D.evec : nullptr, n_iter, n, st);
+    if (!rc) rc = upd_multi_launch(P.upd[parity], st);
+    if (!rc) rc = launch_lz_after_update_multi(D.sc, D.red, D.beta, D.alpha, n_iter, n, st);
+    return rc;
+}
+
+// Run all recurrences from v0 for up to n_max[p] steps (pass 1, or the
+// eigenvector pass when acc != nullptr).
+int lzb_run(const hphi_ham* const* H, int n, int dtype, const void* const* v0, void* const* A, void* const* Bv,
+            LzBatch& D, const int* n_max, double tol, void* const* acc, bool use_graph, int n_iter, hipStream_t st) {
+    int N = 0;
+    for (int p = 0; p < n; ++p) {
+        const int64_t dim = H[p]->basis->dim;
+        const int grid = stream_grid_for(dim * (dtype_complex(dtype) ? 2 : 1));
+        double* red = D.red + size_t(kNQ) * p;
+        int rc = launch_copy_norm(v0[p], A[p], dim, dtype, D.spart, grid, red, st);
+        if (!rc) rc = launch_lz_init(D.sc + p, red, tol, n_max[p], st);
+        if (rc) return rc;
+        if (n_max[p] > N) N = n_max[p];
+    }
+    BatchPlans P;
+    int rc = lzb_plans(H, n, dtype, A, Bv, D, acc, P);
+    if (!rc) rc = lzb_iteration(P, n, 0, true, D, acc != nullptr, n_iter, st);
+    int k = 1;
+    if (!rc && use_graph && N >= 3) {
+        hipStream_t cs;
+        rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
+        if (!rc) {
+            hipEvent_t ev;
+            (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            (void)hipEventRecord(ev, st);
+            (void)hipStreamWaitEvent(cs, ev, 0);
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+            if (!rc) {
+                int r1 = lzb_iteration(P, n, 1, false, D, acc != nullptr, n_iter, cs);
+                int r2 = r1 ? r1 : lzb_iteration(P, n, 0, false, D, acc != nullptr, n_iter, cs);
+                hipError_t e = hipStreamEndCapture(cs, &g);
+                rc = r2 ? r2 : check_hip(e, "end capture");
+            }
+            if (!rc) rc = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+            for (; !rc && k + 2 <= N; k += 2) rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
+            (void)hipEventRecord(ev, cs);
+            (void)hipStreamWaitEvent(st, ev, 0);
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamSynchronize(cs);
+            (void)hipStreamDestroy(cs);
+            (void)hipEventDestroy(ev);
+        }
+    }
+    for (; !rc && k < N; ++k) rc = lzb_iteration(P, n, k & 1, false, D, acc != nullptr, n_iter, st);
+    // plans are read by kernels still in flight: release after the stream drains
+    hipError_t e = hipStreamSynchronize(st);
+    P.release();
+    if (!rc) rc = check_hip(e, "batched lanczos sync");
+    return rc;
+}
+
+// FP64 check of a Ritz vector x: <x|x>, <x|Hx>, |Hx|^2, then |Hx - E x|^2
+int refine_one(const hphi_ham* H, const void* x, int x_dtype, double* red, hphi_lanczos_result& r,
+               hipStream_t st) {
+    HvLaunch L{};
+    L.ham = H;
+    L.v = x;
+    L.u = nullptr;
+    L.a = 1.0;
+    L.b = 0.0;
+    L.nvec = 1;
+    L.dtype = x_dtype;
+    L.reduce_out = red;
+    int rc = launch_hv(L, st);
+    double q[4];
+    if (!rc) rc = check_hip(hipMemcpyAsync(q, red, 32, hipMemcpyDeviceToHost, st), "copy red");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
+    if (rc) return rc;
+    const double E = q[1] / q[0];
+    r.e0_refined = E;
+    r.variance = q[2] / q[0] - E * E;
+    L.b = -E;
+    rc = launch_hv(L, st);
+    if (!rc) rc = check_hip(hipMemcpyAsync(q, red, 32, hipMemcpyDeviceToHost, st), "copy red");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
+    if (rc) return rc;
+    r.residual = std::sqrt(q[3] / q[0]);
+    return HPHI_OK;
+}
+
+// Batched Lanczos (all problems in one launch per kernel and step).
+int lanczos_batched(const hphi_ham* const* hams, int n, const hphi_lanczos_opts& o, double tol,
+                    const void* const* v0, void* const* work, void* const* x_out, hphi_lanczos_result* res,
+                    hipStream_t st) {
+    const int x_dtype = dtype_complex(o.dtype) ? HPHI_C128 : HPHI_F64;
+    LzBatch D;
+    int rc = lzb_alloc(D, n, o.n_iter);
+    if (rc) return rc;
+    std::vector<int> n_max(n);
+    std::vector<void*> A(n), Bv(n);
+    for (int h = 0; h < n; ++h) {
+        const int64_t dim = hams[h]->basis->dim;
+        n_max[h] = int(dim < o.n_iter ? dim : o.n_iter);
+        A[h] = work[h];
+        Bv[h] = (char*)work[h] + size_t(dim) * dtype_size(o.dtype);
+    }
+    rc = lzb_run(hams, n, o.dtype, v0, A.data(), Bv.data(), D, n_max.data(), tol, nullptr, o.use_graph != 0,
+                 o.n_iter, st);
+    std::vector<LzScalars> sc(n);
+    std::vector<double> alpha(size_t(n) * o.n_iter), beta(size_t(n) * o.n_iter);
+    if (!rc) rc = check_hip(hipMemcpyAsync(sc.data(), D.sc, size_t(n) * sizeof(LzScalars), hipMemcpyDeviceToHost, st),
+                            "copy scalars");
+    if (!rc) rc = check_hip(hipMemcpyAsync(alpha.data(), D.alpha, alpha.size() * 8, hipMemcpyDeviceToHost, st), "copy alpha");
+    if (!rc) rc = check_hip(hipMemcpyAsync(beta.data(), D.beta, beta.size() * 8, hipMemcpyDeviceToHost, st), "copy beta");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "lanczos sync");
+    std::vector<double> evecs(size_t(n) * o.n_iter, 0.0);
+    std::vector<int> n_done(n, 0);
+    for (int h = 0; h < n && !rc; ++h) {
+        const int nd = sc[h].n_done;
+        n_done[h] = nd;
+        res[h].n_done = nd;
+        res[h].info = (sc[h].breakdown || nd < o.n_iter) ? HPHI_INFO_BREAKDOWN : HPHI_OK;
+        for (int k = 0; k < o.n_iter; ++k) {
+            res[h].alpha[k] = k < nd ? alpha[size_t(h) * o.n_iter + k] : 0.0;
+            res[h].beta[k] = k < nd ? beta[size_t(h) * o.n_iter + k] : 0.0;
+        }
+        if (nd < 1) rc = set_error(HPHI_EINVAL, "hphi_lanczos: zero start vector for problem %d", h);
+        else res[h].e0_ritz = tridiag_lowest(res[h].alpha, res[h].beta, nd, evecs.data() + size_t(h) * o.n_iter);
+        res[h].e0_refined = res[h].variance = res[h].residual = NAN;
+    }
+    if (!rc && o.refine) {
+        // second pass: replay every recurrence and accumulate x = sum_k e~_k v_k
+        rc = check_hip(hipMemcpyAsync(D.evec, evecs.data(), evecs.size() * 8, hipMemcpyHostToDevice, st), "copy evec");
+        for (int h = 0; h < n && !rc; ++h)
+            rc = launch_fill_zero(x_out[h], hams[h]->basis->dim * int64_t(dtype_size(x_dtype)), st);
+        if (!rc) rc = lzb_run(hams, n, o.dtype, v0, A.data(), Bv.data(), D, n_done.data(), tol, x_out,
+                              o.use_graph != 0, o.n_iter, st);
+        for (int h = 0; h < n && !rc; ++h) rc = refine_one(hams[h], x_out[h], x_dtype, D.red, res[h], st);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(D.mem);
+    return rc;
+}
+
+// all problems can share one launch: same coefficient type, space kind and width
+bool batchable(const hphi_ham* const* hams, int n) {
+    if (n < 2 || n > 64) return false;
+    for (int h = 1; h < n; ++h) {
+        if (hams[h]->is_complex != hams[0]->is_complex) return false;
+        if ((hams[h]->basis->dev.sector != 0) != (hams[0]->basis->dev.sector != 0)) return false;
+        if ((hams[h]->basis->nbits > 32) != (hams[0]->basis->nbits > 32)) return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos_opts* opts,
@@ -240,6 +486,7 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
     const double tol = o.breakdown_tol > 0 ? o.breakdown_tol : 1e-13;
     hipStream_t st = (hipStream_t)stream;
     const int x_dtype = dtype_complex(o.dtype) ? HPHI_C128 : HPHI_F64;
+    if (batchable(hams, n_hams)) return lanczos_batched(hams, n_hams, o, tol, v0, work, x_out, res, st);
 
     for (int h = 0; h < n_hams; ++h) {
         const hphi_ham* H = hams[h];
@@ -280,30 +527,8 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
             if (!rc) rc = launch_fill_zero(x_out[h], dim * int64_t(dtype_size(x_dtype)), st);
             if (!rc) rc = lz_run(H, o.dtype, v0[h], A, Bv, D, n, tol, x_out[h], o.use_graph != 0, st);
             if (rc) return fail(rc);
-            // FP64 check of x: <x|x>, <x|Hx>, |Hx|^2, then |Hx - E x|^2
-            HvLaunch L{};
-            L.ham = H;
-            L.v = x_out[h];
-            L.u = nullptr;
-            L.a = 1.0;
-            L.b = 0.0;
-            L.nvec = 1;
-            L.dtype = x_dtype;
-            L.reduce_out = D.red;
-            rc = launch_hv(L, st);
-            double q[4];
-            if (!rc) rc = check_hip(hipMemcpyAsync(q, D.red, 32, hipMemcpyDeviceToHost, st), "copy red");
-            if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
+            rc = refine_one(H, x_out[h], x_dtype, D.red, res[h], st);
             if (rc) return fail(rc);
-            const double E = q[1] / q[0];
-            res[h].e0_refined = E;
-            res[h].variance = q[2] / q[0] - E * E;
-            L.b = -E;
-            rc = launch_hv(L, st);
-            if (!rc) rc = check_hip(hipMemcpyAsync(q, D.red, 32, hipMemcpyDeviceToHost, st), "copy red");
-            if (!rc) rc = check_hip(hipStreamSynchronize(st), "refine sync");
-            if (rc) return fail(rc);
-            res[h].residual = std::sqrt(q[3] / q[0]);
         }
         (void)hipFree(D.mem);
     }

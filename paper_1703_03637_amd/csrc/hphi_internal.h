@@ -136,7 +136,9 @@ struct hphi_ham {
     int n_sites = 0;
     bool is_complex = false;
     std::vector<hphi::DevOp> ops;
-    hphi::DevOp* d_ops = nullptr;
+    hphi::DevOp* d_ops = nullptr;  // ops padded with inert entries to n_ops_pad
+    int n_ops_pad = 0;            // multiple of 4
+    double* d_ptab = nullptr;     // [n_ops_pad][4 patterns][Re c, Im c, d, 0]
     int grid = 0;                 // persistent grid of the product kernels
     double* d_partials = nullptr; // [kMaxGrid][kNQ * kMaxNvec]
     double* d_red = nullptr;      // [kNQ * kMaxNvec]
@@ -205,6 +207,59 @@ struct LzScalars {
     int32_t pad;
 };
 int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipStream_t st);
+
+// ---- several problems per launch (batched Lanczos over uneven sectors)
+struct RedDesc {             // reduce partials[n_parts][nq] into out[nq]
+    const double* partials;
+    int n_parts;
+    int pad;
+    double* out;
+    const int* stop;
+};
+struct UpdDesc {             // y += c2 x, |y|^2 partials, acc += ec x
+    void* y;
+    const void* x;
+    int64_t n;               // scalars
+    const double* c2;
+    double* acc;
+    const double* ec;
+    double* partials;        // set by the plan
+    const int* stop;
+};
+// Launch plan of one batched product: per-problem arguments, block ranges
+// (multiples of 8) and reductions, uploaded once and replayed by graphs.
+struct MultiPlan {
+    int n = 0;
+    int grid = 0;
+    size_t lds = 0;
+    bool gtab = false;
+    int dtype = 0;
+    bool cc = false, sector = false, w64 = false;
+    void* mem = nullptr;     // device: args, begin, partials, reductions
+    const void* d_args = nullptr;
+    const int* d_begin = nullptr;
+    const RedDesc* d_red = nullptr;
+};
+// Problems must agree on dtype, coefficient type, sector/full space and
+// configuration width (else HPHI_EINVAL); nvec must be 1.
+int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out);
+int hv_multi_launch(const MultiPlan& P, hipStream_t st);
+struct UpdPlan {
+    int n = 0;
+    int grid = 0;
+    bool fp64 = true;
+    void* mem = nullptr;
+    const UpdDesc* d_desc = nullptr;
+    const int* d_begin = nullptr;
+    const RedDesc* d_red = nullptr;
+};
+// red_out[p]: device [1] receiving |y_p|^2
+int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int dtype, UpdPlan* out);
+int upd_multi_launch(const UpdPlan& P, hipStream_t st);
+int launch_lz_after_hv_multi(LzScalars* sc, const double* red, double* alpha, const double* evec, int stride, int n,
+                             hipStream_t st);
+int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta, const double* alpha, int stride,
+                                 int n, hipStream_t st);
 int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec,
                        hipStream_t st);
 int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st);

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <vector>
 
 #include "hphi_internal.h"
 
@@ -162,8 +163,9 @@ __host__ __device__ constexpr void vec_lane(int g, int& sub, int& bi) {
 
 struct HvArgs {
     BasisDev bs;
-    const DevOp* ops;
+    const DevOp* ops;    // padded to n_ops (a multiple of 4)
     int n_ops;
+    const double* ptab;  // [n_ops][4][Re c, Im c, d, 0] pattern table
     const void* v;
     void* u;
     const void* y;
@@ -279,12 +281,23 @@ __device__ __forceinline__ void wave_reduce_quantities(const double (&x)[NE], co
     wq[3] += wave_reduce_rows<double, VPL, LPR>(q, lane);
 }
 
+// dynamic LDS of the product kernels (pattern tables, staged rank tables)
+extern __shared__ double lds_dyn[];
+
+// Bytes of LDS the single-pass product stages: the pattern table, and on a
+// sector basis both split rank tables.  Above kLdsStageBytes everything is
+// read from global memory instead (GTAB).
+constexpr size_t kLdsStageBytes = 64 * 1024;
+
+// Body of the single-pass product for the block `blk` of `nblk` (a multiple
+// of 8) working on the problem A.
 // S: storage scalar, CPLX: complex vectors, CCOEF: complex coefficients,
 // SECTOR: split-table rank, B: interleaved vectors per row, LPR: lanes per
 // row (each lane owns B/LPR of the vectors, in interleaved chunks),
-// W64: configurations above 32 bits.
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
-__global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
+// W64: configurations above 32 bits, GTAB: tables read from global memory
+// (else staged in LDS).
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+__device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const int nblk) {
     using ST = typename StateT<W64>::type;
     constexpr int NC = CPLX ? 2 : 1;
     constexpr int VPL = B / LPR;          // vectors per lane
@@ -302,11 +315,39 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     const S* __restrict__ v = static_cast<const S*>(A.v);
     S* __restrict__ u = static_cast<S*>(A.u);
     const S* __restrict__ y = static_cast<const S*>(A.y);
-    // operator table through the constant address space: uniform indices
-    // become scalar loads, per-lane pattern selects become v_cndmask
+    // operator records through the constant address space: uniform indices
+    // become scalar loads
     const ConstOp* ops = (const ConstOp*)(A.ops);
     const BasisDev& bs = A.bs;
     const int n_ops = A.n_ops;
+
+    // pattern table and (sector) rank tables: staged in LDS, or global
+    const double* tab;
+    const int64_t* jhi = nullptr;
+    const uint32_t* jlo = nullptr;
+    if constexpr (GTAB) {
+        tab = A.ptab;
+        if constexpr (SECTOR) {
+            jhi = bs.j_hi;
+            jlo = bs.j_lo;
+        }
+    } else {
+        double* lt = lds_dyn;
+        for (int i = int(threadIdx.x); i < n_ops * 16; i += kBlock) lt[i] = A.ptab[i];
+        tab = lt;
+        if constexpr (SECTOR) {
+            int64_t* lh = reinterpret_cast<int64_t*>(lt + n_ops * 16);
+            const int n_hi = 1 << (bs.nbits - bs.b_lo);
+            for (int i = int(threadIdx.x); i < n_hi; i += kBlock) lh[i] = bs.j_hi[i];
+            uint32_t* ll = reinterpret_cast<uint32_t*>(lh + n_hi);
+            const int n_lo = 1 << bs.b_lo;
+            for (int i = int(threadIdx.x); i < n_lo; i += kBlock) ll[i] = bs.j_lo[i];
+            jhi = lh;
+            jlo = ll;
+        }
+        __syncthreads();
+    }
+
     // all arithmetic in FP64: FP32 types are a storage format only
     double sx[VPL], cy[VPL];
 #pragma unroll
@@ -317,16 +358,24 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
     }
     const double ca = A.a, cb = A.b;
 
-    // XCD-aware tile range
-    const int xcd = blockIdx.x & 7;
-    const int waves_x = int(gridDim.x >> 3) * kWavesPerBlock;
-    const int wl = int(blockIdx.x >> 3) * kWavesPerBlock + wave;
+    // XCD-aware tile range: blocks blk, blk + 8, ... share an XCD and sweep
+    // its contiguous eighth of the tiles
+    const int xcd = blk & 7;
+    const int waves_x = (nblk >> 3) * kWavesPerBlock;
+    const int wl = (blk >> 3) * kWavesPerBlock + wave;
     const int64_t T = bs.n_tiles;
     const int64_t Tx = (T + 7) >> 3;
     const int64_t t_begin = xcd * Tx;
     const int64_t t_end = (t_begin + Tx < T) ? t_begin + Tx : T;
 
     double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
+    // gathered rows stay live across operators: a lane whose element is zero
+    // skips its load and multiplies the previous (finite) values by 0.0
+    alignas(16) S g[4][NE];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) g[k][e] = S(0);
 
     for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
         int64_t k_hi = 0, tile_row0 = 0, cnt = kTile;
@@ -361,47 +410,59 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
             for (int e = 0; e < NE; ++e) acc[e] = 0.0;
             double dsum = 0.0;
 
-            if (valid) {
-                for (int o = 0; o < n_ops; ++o) {
-                    const ConstOp& op = ops[o];
+            // operators in groups of 4: decode all, issue every gather, then
+            // accumulate (FP64 coefficients and sums)
+            for (int o = 0; o < n_ops; o += 4) {
+                double crk[4], cik[4];
+                int64_t ik[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const ConstOp& op = ops[o + k];
                     const uint32_t bi = op.bi, bj = op.bj;
                     const uint64_t xmask = op.xmask, smask = op.smask;
-                    const bool b0 = bit_at<W64>(s, bi) != 0;
-                    const bool b1 = bit_at<W64>(s, bj) != 0;
-                    const double d0 = op.d[0], d1 = op.d[1], d2 = op.d[2], d3 = op.d[3];
-                    dsum += b1 ? (b0 ? d3 : d2) : (b0 ? d1 : d0);
-                    if (xmask == 0) continue;
-                    double cr, ci = 0.0;
-                    const double c0 = op.cr[0], c1 = op.cr[1], c2 = op.cr[2], c3 = op.cr[3];
-                    cr = b1 ? (b0 ? c3 : c2) : (b0 ? c1 : c0);
-                    if constexpr (CCOEF) {
-                        const double e0 = op.ci[0], e1 = op.ci[1], e2 = op.ci[2], e3 = op.ci[3];
-                        ci = b1 ? (b0 ? e3 : e2) : (b0 ? e1 : e0);
+                    const uint32_t pat = bit_at<W64>(s, bi) | (bit_at<W64>(s, bj) << 1);
+                    const double* te = tab + ((o + k) * 4 + int(pat)) * 4;
+                    double cr = te[0];
+                    double ci = CCOEF ? te[1] : 0.0;
+                    dsum += te[2];
+                    if (smask != 0 && parity_masked<W64>(s, smask)) {
+                        cr = -cr;
+                        ci = -ci;
                     }
-                    const bool active = CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0);
-                    if (active) {
-                        const ST t = s ^ ST(xmask);
-                        if (smask != 0 && parity_masked<W64>(s, smask)) {
-                            cr = -cr;
-                            ci = -ci;
-                        }
-                        const int64_t idx = rank_of<SECTOR>(bs, uint64_t(t));
-                        alignas(16) S g[NE];
-                        load_lane<S, NE, LPR>(v, idx, sub, g);
+                    const ST t = s ^ ST(xmask);
+                    int64_t idx;
+                    if constexpr (SECTOR) {
+                        // every lookup stays inside its table; a target outside
+                        // the sector only occurs where the element is zero
+                        idx = jhi[t >> bs.b_lo] + int64_t(jlo[t & ST(bs.mask_lo)]);
+                    } else {
+                        idx = int64_t(t);
+                    }
+                    crk[k] = valid ? cr : 0.0;
+                    cik[k] = valid ? ci : 0.0;
+                    ik[k] = idx;
+                }
 #pragma unroll
-                        for (int b = 0; b < VPL; ++b) {
-                            if constexpr (CPLX) {
-                                const double gr = double(g[2 * b]), gi = double(g[2 * b + 1]);
-                                if constexpr (CCOEF) {
-                                    acc[2 * b] += cr * gr - ci * gi;
-                                    acc[2 * b + 1] += cr * gi + ci * gr;
-                                } else {
-                                    acc[2 * b] += cr * gr;
-                                    acc[2 * b + 1] += cr * gi;
-                                }
+                for (int k = 0; k < 4; ++k) {
+                    const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                    if (act) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double cr = crk[k], ci = cik[k];
+#pragma unroll
+                    for (int b = 0; b < VPL; ++b) {
+                        if constexpr (CPLX) {
+                            const double gr = double(g[k][2 * b]), gi = double(g[k][2 * b + 1]);
+                            if constexpr (CCOEF) {
+                                acc[2 * b] += cr * gr - ci * gi;
+                                acc[2 * b + 1] += cr * gi + ci * gr;
                             } else {
-                                acc[b] += cr * double(g[b]);
+                                acc[2 * b] += cr * gr;
+                                acc[2 * b + 1] += cr * gi;
                             }
+                        } else {
+                            acc[b] += cr * double(g[k][b]);
                         }
                     }
                 }
@@ -466,8 +527,26 @@ __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
         double acc = 0.0;
 #pragma unroll
         for (int w = 0; w < kWavesPerBlock; ++w) acc += sh[w][k][L];
-        A.partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = acc;
+        A.partials[size_t(blk) * (kNQ * B) + threadIdx.x] = acc;
     }
+}
+
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+__global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
+    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>(A, int(blockIdx.x), int(gridDim.x));
+}
+
+// Several problems in one launch (uneven sector sizes): problem p owns the
+// blocks begin[p] .. begin[p+1]-1 (multiples of 8, so block & 7 still
+// names the XCD) and its own partials.
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+__global__ __launch_bounds__(kBlock) void hv_multi_kernel(const HvArgs* __restrict__ probs,
+                                                          const int* __restrict__ begin, int n_probs) {
+    int p = 0;
+    for (int q = 1; q < n_probs; ++q)
+        if (int(blockIdx.x) >= begin[q]) p = q;
+    const HvArgs A = probs[p];
+    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>(A, int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,9 +588,6 @@ struct HvwArgs {
     const int* stop;
     double* partials;
 };
-
-// per-block pattern table of the windowed product (dynamic LDS)
-extern __shared__ double lds_tab[];
 
 template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
 __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
@@ -565,14 +641,14 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
         const int q = i & 3;
         const double c0 = rec.c[0], c1 = rec.c[1], c2 = rec.c[2], c3 = rec.c[3];
         const double d0 = rec.d[0], d1 = rec.d[1], d2 = rec.d[2], d3 = rec.d[3];
-        lds_tab[i * TE] = sel4(q, c0, c1, c2, c3);
+        lds_dyn[i * TE] = sel4(q, c0, c1, c2, c3);
         if constexpr (CCOEF) {
             const double e0 = rec.ci[0], e1 = rec.ci[1], e2 = rec.ci[2], e3 = rec.ci[3];
-            lds_tab[i * TE + 1] = sel4(q, e0, e1, e2, e3);
-            lds_tab[i * TE + 2] = sel4(q, d0, d1, d2, d3);
-            lds_tab[i * TE + 3] = 0.0;
+            lds_dyn[i * TE + 1] = sel4(q, e0, e1, e2, e3);
+            lds_dyn[i * TE + 2] = sel4(q, d0, d1, d2, d3);
+            lds_dyn[i * TE + 3] = 0.0;
         } else {
-            lds_tab[i * TE + 1] = sel4(q, d0, d1, d2, d3);
+            lds_dyn[i * TE + 1] = sel4(q, d0, d1, d2, d3);
         }
     }
     __syncthreads();
@@ -622,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                     const ConstKOp& rec = kops[A.kop_begin + o + k];
                     const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj;
                     const uint32_t pat = __builtin_amdgcn_ubfe(s, bi, 1u) | (__builtin_amdgcn_ubfe(s, bj, 1u) << 1);
-                    const double* te = lds_tab + ((o + k) * 4 + int(pat)) * TE;
+                    const double* te = lds_dyn + ((o + k) * 4 + int(pat)) * TE;
                     double cr = te[0], ci = 0.0;
                     if constexpr (CCOEF) {
                         ci = te[1];
@@ -737,12 +813,9 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     }
 }
 
-// out[q] = sum over g of partials[g * nq + q], fixed order; one block per q.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials, int n_parts,
-                                                              int nq, double* __restrict__ out,
-                                                              const int* stop) {
-    if (stop && *stop) return;
-    const int q = blockIdx.x;
+// out[q] = sum over g of partials[g * nq + q], fixed order
+__device__ __forceinline__ void reduce_body(const double* __restrict__ partials, int n_parts, int nq, int q,
+                                            double* __restrict__ out) {
     double s = 0.0;
     for (int g = threadIdx.x; g < n_parts; g += 256) s += partials[size_t(g) * nq + q];
     __shared__ double sh[256];
@@ -753,6 +826,25 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
         __syncthreads();
     }
     if (threadIdx.x == 0) out[q] = sh[0];
+}
+
+// one block per quantity q
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials, int n_parts,
+                                                              int nq, double* __restrict__ out,
+                                                              const int* stop) {
+    if (stop && *stop) return;
+    reduce_body(partials, n_parts, nq, int(blockIdx.x), out);
+}
+
+// several problems: block p * nq + q reduces quantity q of problem p
+__global__ __launch_bounds__(256) void reduce_multi_kernel(const RedDesc* __restrict__ d, int nq) {
+    const int p = int(blockIdx.x) / nq, q = int(blockIdx.x) % nq;
+    const double* partials = d[p].partials;
+    const int n_parts = d[p].n_parts;
+    double* out = d[p].out;
+    const int* stop = d[p].stop;
+    if (stop && *stop) return;
+    reduce_body(partials, n_parts, nq, q, out);
 }
 
 // ---- element export (same operator evaluation as hv_kernel, FP64 values)
@@ -857,18 +949,17 @@ __global__ __launch_bounds__(256) void copy_norm_kernel(const S* __restrict__ sr
     if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
 }
 
-// y += c2 * x, |y|^2; optionally acc += ecoef * x (FP64 accumulator)
+// y += c2 * x, |y|^2; optionally acc += ecoef * x (FP64 accumulator);
+// block blk of nblk, one partial per block
 template <typename S>
-__global__ __launch_bounds__(256) void lanczos_update_kernel(S* __restrict__ y, const S* __restrict__ x, int64_t n,
-                                                             const double* __restrict__ c2p,
-                                                             double* __restrict__ acc,
-                                                             const double* __restrict__ ecp,
-                                                             double* __restrict__ partials, const int* stop) {
-    if (stop && *stop) return;
+__device__ __forceinline__ void update_body(S* __restrict__ y, const S* __restrict__ x, int64_t n,
+                                            const double* __restrict__ c2p, double* __restrict__ acc,
+                                            const double* __restrict__ ecp, double* __restrict__ partials,
+                                            int blk, int nblk) {
     const double c2 = *c2p;
     const double ec = acc ? *ecp : 0.0;
     double s = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    for (int64_t i = int64_t(blk) * 256 + threadIdx.x; i < n; i += int64_t(nblk) * 256) {
         const double xv = double(x[i]);
         const S w = S(double(y[i]) + c2 * xv);
         y[i] = w;
@@ -882,7 +973,30 @@ __global__ __launch_bounds__(256) void lanczos_update_kernel(S* __restrict__ y, 
         if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) partials[blk] = sh[0];
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void lanczos_update_kernel(S* __restrict__ y, const S* __restrict__ x, int64_t n,
+                                                             const double* __restrict__ c2p,
+                                                             double* __restrict__ acc,
+                                                             const double* __restrict__ ecp,
+                                                             double* __restrict__ partials, const int* stop) {
+    if (stop && *stop) return;
+    update_body<S>(y, x, n, c2p, acc, ecp, partials, int(blockIdx.x), int(gridDim.x));
+}
+
+// several problems: problem p owns blocks begin[p] .. begin[p+1]-1
+template <typename S>
+__global__ __launch_bounds__(256) void lanczos_update_multi_kernel(const UpdDesc* __restrict__ d,
+                                                                   const int* __restrict__ begin, int n_probs) {
+    int p = 0;
+    for (int q = 1; q < n_probs; ++q)
+        if (int(blockIdx.x) >= begin[q]) p = q;
+    const UpdDesc D = d[p];
+    if (D.stop && *D.stop) return;
+    update_body<S>(static_cast<S*>(D.y), static_cast<const S*>(D.x), D.n, D.c2, D.acc, D.ec, D.partials,
+                   int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
 }
 
 __global__ void fill_zero_kernel(uint32_t* __restrict__ p, int64_t n_words) {
@@ -917,16 +1031,31 @@ __global__ void lz_init_kernel(LzScalars* sc, const double* red, double tol, int
     sc->breakdown = nn > 0.0 ? 0 : 1;
 }
 
-__global__ void lz_after_hv_kernel(LzScalars* sc, const double* red, double* alpha, const double* evec) {
+// per-problem scalar steps; thread p handles problem p (red: kNQ per
+// problem, alpha/beta/evec: `stride` per problem)
+__global__ void lz_after_hv_kernel(LzScalars* scs, const double* reds, double* alphas, const double* evecs,
+                                   int stride, int n) {
+    const int p = int(threadIdx.x);
+    if (p >= n) return;
+    LzScalars* sc = scs + p;
     if (sc->stop) return;
+    const double* red = reds + kNQ * p;
+    double* alpha = alphas + size_t(stride) * p;
     const double a = red[1];          // Re<v_k|H v_k>, v_k = s_cur * X
     alpha[sc->k] = a;
     sc->c2 = -a * sc->s_cur;
-    sc->ecoef = evec ? evec[sc->k] * sc->s_cur : 0.0;
+    sc->ecoef = evecs ? evecs[size_t(stride) * p + sc->k] * sc->s_cur : 0.0;
 }
 
-__global__ void lz_after_update_kernel(LzScalars* sc, const double* red, double* beta, const double* alpha) {
+__global__ void lz_after_update_kernel(LzScalars* scs, const double* reds, double* betas, const double* alphas,
+                                       int stride, int n) {
+    const int p = int(threadIdx.x);
+    if (p >= n) return;
+    LzScalars* sc = scs + p;
     if (sc->stop) return;
+    const double* red = reds + kNQ * p;
+    double* beta = betas + size_t(stride) * p;
+    const double* alpha = alphas + size_t(stride) * p;
     const int k = sc->k;
     const double b = sqrt(red[0]);
     beta[k] = b;
@@ -993,15 +1122,34 @@ static int make_grid(int occ, const Schedule& sc, int64_t tiles) {
     return int(g);
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
-static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
+// LDS the single-pass product stages for this problem (0 = tables stay global)
+static size_t hv_stage_bytes(const hphi_ham* H, bool sector) {
+    size_t b = size_t(H->n_ops_pad) * 16 * sizeof(double);
+    if (sector) {
+        const int b_lo = H->basis->dev.b_lo, b_hi = H->basis->nbits - b_lo;
+        if (b_lo > 20 || b_hi > 20) return kLdsStageBytes + 1;
+        b += (size_t(1) << b_hi) * 8 + (size_t(1) << b_lo) * 4;
+    }
+    return b;
+}
+
+// resident blocks per CU once `lds` bytes of dynamic LDS are taken
+static int occupancy_with_lds(int occ, size_t lds) {
+    constexpr size_t kLdsPerCu = 160 * 1024, kStatic = 8 * 1024;
+    const int by_lds = int(kLdsPerCu / (lds + kStatic));
+    return by_lds < occ ? (by_lds < 1 ? 1 : by_lds) : occ;
+}
+
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStream_t st) {
     const hphi_ham* H = L.ham;
-    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64>);
-    const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
+    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>);
+    const int grid = make_grid(occupancy_with_lds(occ, lds), sc, H->basis->dev.n_tiles);
     HvArgs A;
     A.bs = H->basis->dev;
     A.ops = H->d_ops;
-    A.n_ops = int(H->ops.size());
+    A.n_ops = H->n_ops_pad;
+    A.ptab = H->d_ptab;
     A.v = L.v;
     A.u = L.u;
     A.y = L.y;
@@ -1011,7 +1159,7 @@ static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
-    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64><<<grid, kBlock, 0, st>>>(A);
+    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB><<<grid, kBlock, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
     if (L.reduce_out) {
@@ -1019,6 +1167,17 @@ static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
         rc = check_hip(hipGetLastError(), "reduce launch");
     }
     return rc;
+}
+
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
+static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
+    if constexpr (W64) {
+        return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
+    } else {
+        const size_t lds = hv_stage_bytes(L.ham, SECTOR);
+        if (lds <= kLdsStageBytes) return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, false>(L, sc, lds, st);
+        return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
+    }
 }
 
 template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
@@ -1256,12 +1415,209 @@ int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipS
 }
 
 int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec, hipStream_t st) {
-    lz_after_hv_kernel<<<1, 1, 0, st>>>(sc, red, alpha, evec);
+    lz_after_hv_kernel<<<1, 64, 0, st>>>(sc, red, alpha, evec, 0, 1);
     return check_hip(hipGetLastError(), "lz_after_hv launch");
 }
 
 int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st) {
-    lz_after_update_kernel<<<1, 1, 0, st>>>(sc, red, beta, alpha);
+    lz_after_update_kernel<<<1, 64, 0, st>>>(sc, red, beta, alpha, 0, 1);
+    return check_hip(hipGetLastError(), "lz_after_update launch");
+}
+
+// ---------------------------------------------------------------- batched
+
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, bool W64, bool GTAB>
+static int hv_multi_go(const MultiPlan& P, hipStream_t st) {
+    hv_multi_kernel<S, CPLX, CCOEF, SECTOR, 1, 1, W64, GTAB><<<P.grid, kBlock, P.lds, st>>>(
+        static_cast<const HvArgs*>(P.d_args), P.d_begin, P.n);
+    int rc = check_hip(hipGetLastError(), "hv_multi launch");
+    if (rc) return rc;
+    reduce_multi_kernel<<<P.n * kNQ, 256, 0, st>>>(P.d_red, kNQ);
+    return check_hip(hipGetLastError(), "reduce_multi launch");
+}
+
+template <typename S, bool CPLX, bool CCOEF>
+static int hv_multi_s(const MultiPlan& P, hipStream_t st) {
+    if (P.w64) {
+        if (P.sector) return hv_multi_go<S, CPLX, CCOEF, true, true, true>(P, st);
+        return hv_multi_go<S, CPLX, CCOEF, false, true, true>(P, st);
+    }
+    if (P.sector)
+        return P.gtab ? hv_multi_go<S, CPLX, CCOEF, true, false, true>(P, st)
+                      : hv_multi_go<S, CPLX, CCOEF, true, false, false>(P, st);
+    return P.gtab ? hv_multi_go<S, CPLX, CCOEF, false, false, true>(P, st)
+                  : hv_multi_go<S, CPLX, CCOEF, false, false, false>(P, st);
+}
+
+int hv_multi_launch(const MultiPlan& P, hipStream_t st) {
+    switch (P.dtype) {
+        case HPHI_F64: return hv_multi_s<double, false, false>(P, st);
+        case HPHI_F32: return hv_multi_s<float, false, false>(P, st);
+        case HPHI_C128: return P.cc ? hv_multi_s<double, true, true>(P, st) : hv_multi_s<double, true, false>(P, st);
+        case HPHI_C64: return P.cc ? hv_multi_s<float, true, true>(P, st) : hv_multi_s<float, true, false>(P, st);
+    }
+    return set_error(HPHI_EINVAL, "bad dtype %d", P.dtype);
+}
+
+int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out) {
+    if (n < 1 || !out) return set_error(HPHI_EINVAL, "hv_multi_prepare: no problems");
+    MultiPlan P;
+    P.n = n;
+    P.dtype = Ls[0].dtype;
+    P.cc = Ls[0].ham->is_complex;
+    P.sector = Ls[0].ham->basis->dev.sector != 0;
+    P.w64 = Ls[0].ham->basis->nbits > 32;
+    size_t lds = 0;
+    int64_t tiles_total = 0;
+    for (int p = 0; p < n; ++p) {
+        const HvLaunch& L = Ls[p];
+        if (L.nvec != 1 || L.dtype != P.dtype || L.ham->is_complex != P.cc ||
+            (L.ham->basis->dev.sector != 0) != P.sector || (L.ham->basis->nbits > 32) != P.w64)
+            return set_error(HPHI_EINVAL, "hv_multi_prepare: problems differ in dtype, coefficients or space kind");
+        const size_t b = hv_stage_bytes(L.ham, P.sector);
+        if (b > lds) lds = b;
+        tiles_total += L.ham->basis->dev.n_tiles;
+    }
+    P.gtab = P.w64 || lds > kLdsStageBytes;
+    P.lds = P.gtab ? 0 : lds;
+    // blocks: a share of the resident grid proportional to the tiles, at
+    // least 8 and at most what the tiles can use, rounded up to 8
+    int occ = 1;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hv_multi_kernel<double, false, false, true, 1, 1, false, false>,
+                                                       kBlock, 0);
+    if (occ < 1) occ = 1;
+    const int64_t resident = int64_t(occupancy_with_lds(occ, P.lds)) * cu_count();
+    std::vector<int> begin(n + 1, 0);
+    for (int p = 0; p < n; ++p) {
+        const int64_t t = Ls[p].ham->basis->dev.n_tiles;
+        int64_t nb = (resident * t + tiles_total - 1) / (tiles_total > 0 ? tiles_total : 1);
+        const int64_t useful = (t + kWavesPerBlock - 1) / kWavesPerBlock;
+        if (nb > useful) nb = useful;
+        nb = ((nb + 7) / 8) * 8;
+        if (nb < 8) nb = 8;
+        begin[p + 1] = begin[p] + int(nb);
+    }
+    P.grid = begin[n];
+    // device memory: args | begin | partials | reductions
+    const size_t a_bytes = size_t(n) * sizeof(HvArgs);
+    const size_t b_off = (a_bytes + 255) / 256 * 256;
+    const size_t p_off = b_off + (size_t(n + 1) * 4 + 255) / 256 * 256;
+    const size_t r_off = p_off + size_t(P.grid) * kNQ * sizeof(double);
+    const size_t total = r_off + size_t(n) * sizeof(RedDesc);
+    char* mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess) return set_error(HPHI_ENOMEM, "hv_multi_prepare: device memory");
+    std::vector<HvArgs> args(n);
+    std::vector<RedDesc> red(n);
+    double* partials = reinterpret_cast<double*>(mem + p_off);
+    for (int p = 0; p < n; ++p) {
+        const HvLaunch& L = Ls[p];
+        HvArgs& A = args[p];
+        A.bs = L.ham->basis->dev;
+        A.ops = L.ham->d_ops;
+        A.n_ops = L.ham->n_ops_pad;
+        A.ptab = L.ham->d_ptab;
+        A.v = L.v;
+        A.u = L.u;
+        A.y = L.y;
+        A.cy = L.cy;
+        A.sx = L.sx;
+        A.a = L.a;
+        A.b = L.b;
+        A.stop = L.stop;
+        A.partials = partials + size_t(begin[p]) * kNQ;
+        red[p].partials = A.partials;
+        red[p].n_parts = begin[p + 1] - begin[p];
+        red[p].pad = 0;
+        red[p].out = L.reduce_out;
+        red[p].stop = L.stop;
+    }
+    hipError_t e = hipMemcpy(mem, args.data(), a_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + b_off, begin.data(), size_t(n + 1) * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + r_off, red.data(), size_t(n) * sizeof(RedDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return check_hip(e, "hv_multi_prepare: upload");
+    }
+    P.mem = mem;
+    P.d_args = mem;
+    P.d_begin = reinterpret_cast<const int*>(mem + b_off);
+    P.d_red = reinterpret_cast<const RedDesc*>(mem + r_off);
+    *out = P;
+    return HPHI_OK;
+}
+
+int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int dtype, UpdPlan* out) {
+    if (n < 1 || !out) return set_error(HPHI_EINVAL, "upd_multi_prepare: no problems");
+    UpdPlan P;
+    P.n = n;
+    P.fp64 = dtype == HPHI_F64 || dtype == HPHI_C128;
+    int64_t total = 0;
+    for (int p = 0; p < n; ++p) total += descs[p].n;
+    std::vector<int> begin(n + 1, 0);
+    const int64_t target = 1024;   // blocks of the streaming kernel in all
+    for (int p = 0; p < n; ++p) {
+        int64_t nb = total > 0 ? (target * descs[p].n + total - 1) / total : 1;
+        const int64_t useful = (descs[p].n + 255) / 256;
+        if (nb > useful) nb = useful;
+        if (nb < 1) nb = 1;
+        begin[p + 1] = begin[p] + int(nb);
+    }
+    P.grid = begin[n];
+    const size_t d_bytes = size_t(n) * sizeof(UpdDesc);
+    const size_t b_off = (d_bytes + 255) / 256 * 256;
+    const size_t p_off = b_off + (size_t(n + 1) * 4 + 255) / 256 * 256;
+    const size_t r_off = p_off + size_t(P.grid) * sizeof(double);
+    const size_t total_b = r_off + size_t(n) * sizeof(RedDesc);
+    char* mem = nullptr;
+    if (hipMalloc(&mem, total_b) != hipSuccess) return set_error(HPHI_ENOMEM, "upd_multi_prepare: device memory");
+    std::vector<UpdDesc> d(descs, descs + n);
+    std::vector<RedDesc> red(n);
+    double* partials = reinterpret_cast<double*>(mem + p_off);
+    for (int p = 0; p < n; ++p) {
+        d[p].partials = partials + begin[p];
+        red[p].partials = d[p].partials;
+        red[p].n_parts = begin[p + 1] - begin[p];
+        red[p].pad = 0;
+        red[p].out = red_out[p];
+        red[p].stop = d[p].stop;
+    }
+    hipError_t e = hipMemcpy(mem, d.data(), d_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + b_off, begin.data(), size_t(n + 1) * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + r_off, red.data(), size_t(n) * sizeof(RedDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return check_hip(e, "upd_multi_prepare: upload");
+    }
+    P.mem = mem;
+    P.d_desc = reinterpret_cast<const UpdDesc*>(mem);
+    P.d_begin = reinterpret_cast<const int*>(mem + b_off);
+    P.d_red = reinterpret_cast<const RedDesc*>(mem + r_off);
+    *out = P;
+    return HPHI_OK;
+}
+
+int upd_multi_launch(const UpdPlan& P, hipStream_t st) {
+    if (P.fp64)
+        lanczos_update_multi_kernel<double><<<P.grid, 256, 0, st>>>(P.d_desc, P.d_begin, P.n);
+    else
+        lanczos_update_multi_kernel<float><<<P.grid, 256, 0, st>>>(P.d_desc, P.d_begin, P.n);
+    int rc = check_hip(hipGetLastError(), "update_multi launch");
+    if (rc) return rc;
+    reduce_multi_kernel<<<P.n, 256, 0, st>>>(P.d_red, 1);
+    return check_hip(hipGetLastError(), "reduce_multi launch");
+}
+
+int launch_lz_after_hv_multi(LzScalars* sc, const double* red, double* alpha, const double* evec, int stride, int n,
+                             hipStream_t st) {
+    const int threads = (n + 63) / 64 * 64;
+    lz_after_hv_kernel<<<1, threads, 0, st>>>(sc, red, alpha, evec, stride, n);
+    return check_hip(hipGetLastError(), "lz_after_hv launch");
+}
+
+int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta, const double* alpha, int stride,
+                                 int n, hipStream_t st) {
+    const int threads = (n + 63) / 64 * 64;
+    lz_after_update_kernel<<<1, threads, 0, st>>>(sc, red, beta, alpha, stride, n);
     return check_hip(hipGetLastError(), "lz_after_update launch");
 }
 
