@@ -116,7 +116,7 @@ def measured_traffic(sched):
         got = sched["pinned"]
     elif isinstance(sched, dict):
         got = ",".join(str(sched[k]) for k in ("windowed", "window_kb", "max_passes", "lanes_per_row",
-                                                "blocks_per_cu"))
+                                                "blocks_per_cu", "stage_tables"))
     else:
         got = None
     if want != got:
@@ -132,11 +132,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--schedule", default="",
-                    help="pin the product schedule 'windowed,window_kb,max_passes,lanes_per_row,blocks_per_cu' "
-                         "for both paths instead of autotuning (used for profiling runs)")
+                    help="pin the product schedule 'windowed,window_kb,max_passes,lanes_per_row,blocks_per_cu"
+                         "[,stage_tables]' for both paths instead of autotuning (used for profiling runs)")
     args = ap.parse_args()
     if args.schedule:
-        keys = ("HPHI_WINDOWED", "HPHI_L2_WINDOW_KB", "HPHI_PASSES", "HPHI_LPR", "HPHI_BLOCKS_PER_CU")
+        keys = ("HPHI_WINDOWED", "HPHI_L2_WINDOW_KB", "HPHI_PASSES", "HPHI_LPR", "HPHI_BLOCKS_PER_CU",
+                "HPHI_STAGE_TABLES")
         for k, val in zip(keys, args.schedule.split(",")):
             os.environ[k] = val
     if args.gpus != 1:

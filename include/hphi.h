@@ -195,13 +195,15 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes,
  * gathering from v itself or from staged copies of v in each pass's row
  * order, or a single natural-order pass; lanes per row (nvec >= 8); resident blocks
- * per CU -- and pins the fastest for this (ham, nvec, dtype): later
+ * per CU, table placement -- and pins the fastest for this (ham, nvec, dtype): later
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different
  * schedule may change the last bits of the reductions.  sched_out (host,
- * may be NULL) receives 6 ints: windowed (0: single pass, 1: windowed,
+ * may be NULL) receives 7 ints: windowed (0: single pass, 1: windowed,
  * 2: windowed with staged copies), window_kb, max_passes,
- * lanes_per_row, blocks_per_cu, microseconds per product call.  If the
+ * lanes_per_row, blocks_per_cu, stage_tables (single-pass kernel: 1 =
+ * pattern and rank tables staged in LDS when they fit, 0 = read from
+ * global memory), microseconds per product call.  If the
  * environment variable HPHI_TUNE_CACHE names a file, the choice is
  * appended there and reused by later processes for the same device,
  * space and operators.  Synchronizes `stream`. */

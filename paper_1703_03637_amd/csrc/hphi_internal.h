@@ -52,6 +52,7 @@ struct Schedule {
     int max_passes = 3;     // passes of the windowed kernel (1 = natural order)
     int lpr = 0;            // lanes per row (nvec >= 8); 0 = default
     int blocks_per_cu = 0;  // resident blocks per CU; 0 = as many as fit
+    int stage_tables = 1;   // single-pass kernel: stage pattern and rank tables in LDS when they fit
 };
 
 // Compact kernel-side operator of the windowed product (configurations of

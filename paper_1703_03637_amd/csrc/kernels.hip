@@ -20,6 +20,7 @@
 // a fixed-order second-stage kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
@@ -284,6 +285,26 @@ __device__ __forceinline__ void wave_reduce_quantities(const double (&x)[NE], co
 // dynamic LDS of the product kernels (pattern tables, staged rank tables)
 extern __shared__ double lds_dyn[];
 
+// Block-wide copy of `bytes` (a multiple of 4) from global memory to LDS:
+// 16-byte pieces, four loads in flight per thread before their stores.
+__device__ __forceinline__ void stage_to_lds(void* dst, const void* src, size_t bytes) {
+    const size_t n16 = bytes / 16;
+    const uint4* s4 = static_cast<const uint4*>(src);
+    uint4* d4 = static_cast<uint4*>(dst);
+    size_t i = threadIdx.x;
+    for (; i + 3 * kBlock < n16; i += 4 * kBlock) {
+        const uint4 a = s4[i], b = s4[i + kBlock], c = s4[i + 2 * kBlock], d = s4[i + 3 * kBlock];
+        d4[i] = a;
+        d4[i + kBlock] = b;
+        d4[i + 2 * kBlock] = c;
+        d4[i + 3 * kBlock] = d;
+    }
+    for (; i < n16; i += kBlock) d4[i] = s4[i];
+    const uint32_t* s1 = static_cast<const uint32_t*>(src);
+    uint32_t* d1 = static_cast<uint32_t*>(dst);
+    for (size_t k = n16 * 4 + threadIdx.x; k < bytes / 4; k += kBlock) d1[k] = s1[k];
+}
+
 // Bytes of LDS the single-pass product stages: the pattern table, and on a
 // sector basis both split rank tables.  Above kLdsStageBytes everything is
 // read from global memory instead (GTAB).
@@ -333,15 +354,16 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
         }
     } else {
         double* lt = lds_dyn;
-        for (int i = int(threadIdx.x); i < n_ops * 16; i += kBlock) lt[i] = A.ptab[i];
+        stage_to_lds(lt, A.ptab, size_t(n_ops) * 16 * sizeof(double));
         tab = lt;
         if constexpr (SECTOR) {
             int64_t* lh = reinterpret_cast<int64_t*>(lt + n_ops * 16);
             const int n_hi = 1 << (bs.nbits - bs.b_lo);
-            for (int i = int(threadIdx.x); i < n_hi; i += kBlock) lh[i] = bs.j_hi[i];
-            uint32_t* ll = reinterpret_cast<uint32_t*>(lh + n_hi);
+            stage_to_lds(lh, bs.j_hi, size_t(n_hi) * 8);
+            // the low table starts on a 16-byte boundary
+            uint32_t* ll = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lh) + ((size_t(n_hi) * 8 + 15) & ~size_t(15)));
             const int n_lo = 1 << bs.b_lo;
-            for (int i = int(threadIdx.x); i < n_lo; i += kBlock) ll[i] = bs.j_lo[i];
+            stage_to_lds(ll, bs.j_lo, size_t(n_lo) * 4);
             jhi = lh;
             jlo = ll;
         }
@@ -1128,7 +1150,7 @@ static size_t hv_stage_bytes(const hphi_ham* H, bool sector) {
     if (sector) {
         const int b_lo = H->basis->dev.b_lo, b_hi = H->basis->nbits - b_lo;
         if (b_lo > 20 || b_hi > 20) return kLdsStageBytes + 1;
-        b += (size_t(1) << b_hi) * 8 + (size_t(1) << b_lo) * 4;
+        b += (((size_t(1) << b_hi) * 8 + 15) & ~size_t(15)) + (size_t(1) << b_lo) * 4;
     }
     return b;
 }
@@ -1175,7 +1197,8 @@ static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
         return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
     } else {
         const size_t lds = hv_stage_bytes(L.ham, SECTOR);
-        if (lds <= kLdsStageBytes) return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, false>(L, sc, lds, st);
+        if (sc.stage_tables && lds <= kLdsStageBytes)
+            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, false>(L, sc, lds, st);
         return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
     }
 }
@@ -1478,25 +1501,46 @@ int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out) {
         if (b > lds) lds = b;
         tiles_total += L.ham->basis->dev.n_tiles;
     }
-    P.gtab = P.w64 || lds > kLdsStageBytes;
+    const Schedule sc = schedule_for(Ls[0].ham, 1, P.dtype);
+    P.gtab = P.w64 || !sc.stage_tables || lds > kLdsStageBytes;
     P.lds = P.gtab ? 0 : lds;
-    // blocks: a share of the resident grid proportional to the tiles, at
-    // least 8 and at most what the tiles can use, rounded up to 8
+    // blocks: the grid is persistent, so it must fit the resident blocks;
+    // every problem gets one group of 8 blocks and the rest is shared in
+    // proportion to the tiles (largest remainders first), never more than
+    // its tiles can use
     int occ = 1;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hv_multi_kernel<double, false, false, true, 1, 1, false, false>,
-                                                       kBlock, 0);
+    if (P.gtab)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, hv_multi_kernel<double, false, false, true, 1, 1, false, true>, kBlock, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, hv_multi_kernel<double, false, false, true, 1, 1, false, false>, kBlock, 0);
     if (occ < 1) occ = 1;
-    const int64_t resident = int64_t(occupancy_with_lds(occ, P.lds)) * cu_count();
-    std::vector<int> begin(n + 1, 0);
+    int per_cu = occupancy_with_lds(occ, P.lds);
+    if (sc.blocks_per_cu > 0 && sc.blocks_per_cu < per_cu) per_cu = sc.blocks_per_cu;
+    const int64_t groups = std::max<int64_t>(n, int64_t(per_cu) * cu_count() / 8);
+    std::vector<int64_t> units(n, 1), cap(n);
+    std::vector<double> frac(n, 0.0);
+    int64_t left = groups - n;
     for (int p = 0; p < n; ++p) {
         const int64_t t = Ls[p].ham->basis->dev.n_tiles;
-        int64_t nb = (resident * t + tiles_total - 1) / (tiles_total > 0 ? tiles_total : 1);
-        const int64_t useful = (t + kWavesPerBlock - 1) / kWavesPerBlock;
-        if (nb > useful) nb = useful;
-        nb = ((nb + 7) / 8) * 8;
-        if (nb < 8) nb = 8;
-        begin[p + 1] = begin[p] + int(nb);
+        cap[p] = std::max<int64_t>(1, ((t + kWavesPerBlock - 1) / kWavesPerBlock + 7) / 8);
+        const double share = tiles_total > 0 ? double(groups - n) * double(t) / double(tiles_total) : 0.0;
+        const int64_t whole = std::min<int64_t>(int64_t(share), cap[p] - 1);
+        units[p] += whole;
+        frac[p] = share - double(int64_t(share));
+        left -= whole;
     }
+    std::vector<int> order(n);
+    for (int p = 0; p < n; ++p) order[p] = p;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return frac[a] > frac[b] || (frac[a] == frac[b] && a < b); });
+    for (int k = 0; k < n && left > 0; ++k)
+        if (units[order[k]] < cap[order[k]]) {
+            ++units[order[k]];
+            --left;
+        }
+    std::vector<int> begin(n + 1, 0);
+    for (int p = 0; p < n; ++p) begin[p + 1] = begin[p] + int(units[p] * 8);
     P.grid = begin[n];
     // device memory: args | begin | partials | reductions
     const size_t a_bytes = size_t(n) * sizeof(HvArgs);

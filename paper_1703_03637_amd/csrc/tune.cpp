@@ -4,7 +4,7 @@
 // The tuner times candidate schedules of the real product on the caller's
 // buffers -- window budget and number of passes of the windowed full-space
 // kernel with or without staged copies (or the single-pass kernel), lanes
-// per row, resident blocks per CU -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
+// per row, resident blocks per CU, LDS or global tables -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
 // HPHI_TUNE_CACHE set, choices are appended to that file, keyed by a
 // signature of the device, the space and the packed operators, and are
 // reused by later processes without timing.
@@ -38,6 +38,7 @@ Schedule default_schedule(int nvec) {
     const int l = env_int("HPHI_LPR", 0);
     if (nvec >= 8 && (l == 1 || l == 2 || l == 4 || l == 8)) s.lpr = l;
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
+    s.stage_tables = env_int("HPHI_STAGE_TABLES", s.stage_tables) ? 1 : 0;
     if (s.window_kb < 1) s.window_kb = 2048;
     if (s.max_passes < 1) s.max_passes = 1;
     return s;
@@ -71,8 +72,8 @@ bool cache_lookup(const std::string& sig, Schedule& out) {
     while (fgets(line, sizeof(line), f)) {
         char key[300];
         Schedule s;
-        if (sscanf(line, "%299s %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
-                   &s.blocks_per_cu) == 6 &&
+        if (sscanf(line, "%299s %d %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
+                   &s.blocks_per_cu, &s.stage_tables) == 7 &&
             sig == key) {
             out = s;   // the last entry for a key wins
             found = true;
@@ -87,8 +88,8 @@ void cache_store(const std::string& sig, const Schedule& s, double us) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
-            s.blocks_per_cu, us);
+    fprintf(f, "%s %d %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
+            s.blocks_per_cu, s.stage_tables, us);
     fclose(f);
 }
 
@@ -139,7 +140,11 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
             s.windowed = 0;
             s.window_kb = 2048;
             s.max_passes = 1;
-            cands.push_back(s);
+            for (int tables : {1, 0}) {
+                s.stage_tables = tables;
+                cands.push_back(s);
+            }
+            s.stage_tables = 1;
             if (!windowable) continue;
             s.windowed = 1;
             cands.push_back(s);   // single natural pass, compact operators
@@ -204,7 +209,8 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
         sched_out[2] = best.max_passes;
         sched_out[3] = best.lpr;
         sched_out[4] = best.blocks_per_cu;
-        sched_out[5] = int(best_us);
+        sched_out[5] = best.stage_tables;
+        sched_out[6] = int(best_us);
     }
     return HPHI_OK;
 }

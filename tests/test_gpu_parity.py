@@ -588,3 +588,34 @@ def test_batched_lanczos_tri24_all_sectors_full_size():
                 e0 = sla.eigsh(H, k=1, which="SA", tol=1e-12)[0][0]
             assert abs(r["e0_refined"] - e0) <= 1e-8 * max(1.0, abs(e0)), (d, r["e0_refined"], e0)
     assert abs(res[-1]["e0_ritz"] - 72 * 0.25) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["spin_sz_dm", "spin_sz_split3", "ferm_nupndn", "ferm_ntot", "hubbard_3x3",
+                                  "spin_full_complex"])
+@pytest.mark.parametrize("stage", [0, 1])
+@pytest.mark.parametrize("nvec", [1, 8])
+def test_hv_table_placement(monkeypatch, name, stage, nvec):
+    """Pattern and rank tables read from global memory (0) or staged in LDS (1): same FP64 product."""
+    print(f"[gpu] table placement {name} stage={stage} nvec={nvec}", flush=True)
+    monkeypatch.setenv("HPHI_STAGE_TABLES", str(stage))
+    monkeypatch.setenv("HPHI_WINDOWED", "0")
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(300, 300 + nvec)), True)
+    vd = _to_dev(v, torch.complex128)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    u = hp.hphi_hv(ham, vd).cpu().numpy().reshape(len(st), nvec)
+    bound, H = _abs_bound(desc, terms, st, v)
+    ref = H @ v
+    assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref) + 1e-300
+    assert np.all(np.abs(u - ref) <= 1e-12 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("stage", [0, 1])
+def test_batched_lanczos_table_placement(monkeypatch, stage):
+    monkeypatch.setenv("HPHI_STAGE_TABLES", str(stage))
+    terms, descs, x0, res = _tri12_sectors(torch.float64, 60)
+    for d, r in zip(descs, res):
+        e0 = np.linalg.eigvalsh(oh.sparse_h(d, terms).toarray())[0]
+        assert abs(r["e0_refined"] - e0) <= 1e-9 * max(1.0, abs(e0))
