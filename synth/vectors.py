@@ -55,9 +55,11 @@ def device_uniform(dim: int, nvec: int, seed: int, complex_: bool, dtype, device
     g.manual_seed(seed)
     shape = (dim, max(nvec, 1))
     real_dt = torch.float32 if dtype in (torch.float32, torch.complex64) else torch.float64
+    # drawn in place: one allocation of the output size (full-size vectors
+    # reach tens of GB)
     if complex_:
-        x = torch.rand(shape + (2,), generator=g, device=device, dtype=real_dt) * 2 - 1
-        out = torch.view_as_complex(x.contiguous()).to(dtype)
+        x = torch.empty(shape + (2,), device=device, dtype=real_dt).uniform_(-1.0, 1.0, generator=g)
+        out = torch.view_as_complex(x).to(dtype)
     else:
-        out = (torch.rand(shape, generator=g, device=device, dtype=real_dt) * 2 - 1).to(dtype)
+        out = torch.empty(shape, device=device, dtype=real_dt).uniform_(-1.0, 1.0, generator=g).to(dtype)
     return out.reshape(dim) if nvec == 0 else out.contiguous()
