@@ -73,7 +73,9 @@ def run_tpq(hp, ham, psi, steps, warmup, l, torch):
 
 
 def cpu_baseline(w, terms, v_host, dim, nvec, target_s=12.0):
-    """The C oracle on a contiguous row slice, scaled to H.v products/s."""
+    """The C oracle on the host cores for about target_s seconds, scaled to
+    H.v products/s: a contiguous row slice when the whole product would take
+    longer, else repeated whole products."""
     import numpy as np
     from oracle import c_oracle
     rows = np.arange(0, 4096, dtype=np.uint64)
@@ -82,13 +84,17 @@ def cpu_baseline(w, terms, v_host, dim, nvec, target_s=12.0):
     dt = time.perf_counter() - t0
     n = int(min(dim, max(4096, 4096 * target_s / max(dt, 1e-6))))
     rows = np.arange(0, n, dtype=np.uint64)
-    t0 = time.perf_counter()
-    c_oracle.rows_hv(terms, rows, v_host)
-    dt = time.perf_counter() - t0
-    rate = (n / dim) * nvec / dt
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        c_oracle.rows_hv(terms, rows, v_host)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if n < dim or dt >= target_s:
+            break
+    rate = reps * (n / dim) * nvec / dt
+    what = (f"rows 0..{n - 1} of {dim}" if n < dim else f"{reps} whole products ({dim} rows each)")
     return {"value": rate, "unit": "H·v products/s", "cores": c_oracle.threads(), "kind": "oracle",
-            "sample": f"C oracle (hv_oracle.c, OpenMP) rows 0..{n - 1} of {dim} with {nvec} complex64 "
-                      f"vectors, {dt:.1f} s, scaled by dim/rows"}
+            "sample": f"C oracle (hv_oracle.c, OpenMP), {what}, {nvec} complex64 vectors, {dt:.1f} s"}
 
 
 def kernel_source_hash() -> str:
@@ -100,9 +106,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def schedule_key(sched) -> str:
+    if isinstance(sched, dict) and "pinned" in sched:
+        parts = sched["pinned"].split(",")
+        return ",".join(parts + ["1"] * (6 - len(parts)))
+    return ",".join(str(sched[k]) for k in ("windowed", "window_kb", "max_passes", "lanes_per_row",
+                                            "blocks_per_cu", "stage_tables"))
+
+
 def measured_traffic(sched):
-    """HBM bytes per batched product from the committed PMC summary, if it
-    was taken on the current kernel sources and the same schedule; else None."""
+    """HBM bytes per batched product (FETCH_SIZE and WRITE_SIZE, scaled by a
+    copy kernel) from the committed PMC summary, if it was taken on the
+    current kernel sources for this schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_kh_honeycomb24_tpq_b16_c64.json")
     try:
         with open(path) as fh:
@@ -111,17 +126,8 @@ def measured_traffic(sched):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    want = rec.get("schedule")
-    if isinstance(sched, dict) and "pinned" in sched:
-        got = sched["pinned"]
-    elif isinstance(sched, dict):
-        got = ",".join(str(sched[k]) for k in ("windowed", "window_kb", "max_passes", "lanes_per_row",
-                                                "blocks_per_cu", "stage_tables"))
-    else:
-        got = None
-    if want != got:
-        return None
-    return rec.get("hbm_bytes_per_product")
+    entry = rec.get("schedules", {}).get(schedule_key(sched))
+    return None if entry is None else entry.get("hbm_bytes_per_product")
 
 
 def main():
@@ -131,6 +137,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three 1 GiB device copies (reference kernel for the PMC byte counters) and exit")
     ap.add_argument("--schedule", default="",
                     help="pin the product schedule 'windowed,window_kb,max_passes,lanes_per_row,blocks_per_cu"
                          "[,stage_tables]' for both paths instead of autotuning (used for profiling runs)")
@@ -147,6 +155,14 @@ def main():
 
     import numpy as np
     import torch
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "3 copies of 1 GiB (read 1 GiB + write 1 GiB each)"}))
+        return
     import paper_1703_03637_amd as hp
     from synth.configs import workload
     from synth.vectors import device_uniform

@@ -161,9 +161,9 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(HPHI_EDEVICE, "hphi_hv_tune: event creation failed");
-    double best_us = 1e300;
-    Schedule best = default_schedule(int(nvec));
-    for (const Schedule& s : cands) {
+    std::vector<double> times(cands.size(), 1e300);
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        const Schedule& s = cands[ci];
         HvLaunch L{};
         L.ham = ham;
         L.v = v;
@@ -182,15 +182,19 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
         if (rc || hipEventSynchronize(e1) != hipSuccess) continue;
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        const double us = 1e3 * ms / reps;
-        if (us < best_us) {
-            best_us = us;
-            best = s;
-        }
+        times[ci] = 1e3 * ms / reps;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (best_us >= 1e300) return set_error(HPHI_EDEVICE, "hphi_hv_tune: no schedule ran");
+    double fastest = 1e300;
+    for (double t : times) fastest = t < fastest ? t : fastest;
+    if (fastest >= 1e300) return set_error(HPHI_EDEVICE, "hphi_hv_tune: no schedule ran");
+    // timing noise is a few percent: the first candidate within 2% of the
+    // fastest wins, so repeated tuning settles on the same schedule
+    size_t pick = 0;
+    while (times[pick] > fastest * 1.02) ++pick;
+    const Schedule best = cands[pick];
+    const double best_us = times[pick];
     {
         hphi_ham* H = const_cast<hphi_ham*>(ham);
         std::lock_guard<std::mutex> lock(H->plan_mu);
