@@ -146,6 +146,23 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
             P->perm[size_t(p) * 64 + k++] = b;
             in[b] = 1;
         }
+        // next, the outside flip bits of the operators folded into this pass
+        // (most frequent first): their partners are then one or two window
+        // blocks away on the same XCD instead of anywhere in the space (the
+        // top processing bits select the XCD)
+        std::vector<int> cnt(nbits, 0);
+        for (int o = 0; o < n_ops; ++o)
+            if (pass_of[o] == p)
+                for (int b = 0; b < nbits; ++b)
+                    if (!in[b] && ((ops[o].xmask >> b) & 1)) ++cnt[b];
+        std::vector<int> outside;
+        for (int b = 0; b < nbits; ++b)
+            if (cnt[b] > 0) outside.push_back(b);
+        std::stable_sort(outside.begin(), outside.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+        for (int b : outside) {
+            P->perm[size_t(p) * 64 + k++] = b;
+            in[b] = 1;
+        }
         for (int b = 0; b < nbits; ++b)
             if (!in[b]) P->perm[size_t(p) * 64 + k++] = b;
     }
