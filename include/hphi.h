@@ -176,7 +176,8 @@ typedef struct {
 
 /* Matrix-free product over all rows of the space.  v, u: device, dim*nvec
  * elements of `dtype`, interleaved; u must not alias v.  nvec in
- * {1, 2, 4, 8, 16}.  FP32/C64 are storage formats only: every product,
+ * {1, 2, 4, 8, 16}; configurations wider than 32 bits allow nvec <= 4
+ * (HPHI_EINVAL otherwise).  FP32/C64 are storage formats only: every product,
  * row sum and reduction is FP64 with FP64 coefficients, and results are
  * rounded once when stored (a multi-pass schedule also rounds the partial
  * sums it passes between passes).  opts NULL = {1, 0, NULL, NULL}.

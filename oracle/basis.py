@@ -110,3 +110,62 @@ def cns_unrank(r: int, k: int, nbits: int) -> int:
     if r != 0:
         raise ValueError("rank out of range")
     return s
+
+
+# -------------------------------------------- sector rank by counting (any sector kind)
+
+def _completions(desc, p: int, need) -> int:
+    """Configurations of the p bits below position p holding the still-needed
+    particles `need` (a count, or (up, down) for the interleaved fermion sector)."""
+    if desc.sector == "nupndn":
+        n_even = (p + 1) // 2          # even positions 0, 2, ... below p
+        n_odd = p // 2
+        return comb(n_even, need[0]) * comb(n_odd, need[1]) if need[0] >= 0 and need[1] >= 0 else 0
+    return comb(p, need) if need >= 0 else 0
+
+
+def _initial_need(desc):
+    if desc.sector == "nupndn":
+        return (desc.n_up, desc.n_dn)
+    if desc.particle == "spin":
+        return (desc.n_sites + desc.two_sz) // 2
+    return desc.n_tot
+
+
+def _take(desc, need, p):
+    """Needs after placing a particle at position p."""
+    if desc.sector == "nupndn":
+        return (need[0] - 1, need[1]) if p % 2 == 0 else (need[0], need[1] - 1)
+    return need - 1
+
+
+def sector_rank(desc, s: int) -> int:
+    """Index of configuration s in the ascending list of its sector (Sec. 3.1),
+    by counting: for each set bit of s, from the top, the sector configurations
+    that agree with s above it and have a 0 there."""
+    if desc.sector == "none":
+        return int(s)
+    need = _initial_need(desc)
+    r = 0
+    for p in range(n_bits(desc) - 1, -1, -1):
+        if (s >> p) & 1:
+            r += _completions(desc, p, need)
+            need = _take(desc, need, p)
+    return r
+
+
+def sector_unrank(desc, r: int) -> int:
+    """Inverse of sector_rank: greedy from the top bit."""
+    if desc.sector == "none":
+        return int(r)
+    need = _initial_need(desc)
+    s = 0
+    for p in range(n_bits(desc) - 1, -1, -1):
+        zero = _completions(desc, p, need)
+        if r >= zero:
+            r -= zero
+            s |= 1 << p
+            need = _take(desc, need, p)
+    if r != 0:
+        raise ValueError("rank out of range")
+    return s

@@ -36,6 +36,11 @@ def lib():
             fn.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                            C.c_int, C.c_void_p]
             fn.restype = C.c_int
+        L.oracle_hv_rows_counted.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                             C.c_int, C.c_void_p]
+        L.oracle_hv_rows_counted.restype = C.c_int
+        L.oracle_unrank_counted.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.oracle_unrank_counted.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -77,3 +82,46 @@ def rows_hv(terms, rows: np.ndarray, v: np.ndarray, states: np.ndarray | None = 
     if rc != 0:
         raise ValueError("a term leaves the basis")
     return u if v.ndim == 2 else u[:, 0]
+
+
+class _OSector(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nbits", C.c_int32), ("n_a", C.c_int32), ("n_b", C.c_int32)]
+
+
+def _sector(desc):
+    nb = desc.n_sites if desc.particle == "spin" else 2 * desc.n_sites
+    if desc.sector == "none":
+        return _OSector(0, nb, 0, 0)
+    if desc.sector == "nupndn":
+        return _OSector(2, nb, desc.n_up, desc.n_dn)
+    if desc.particle == "spin":
+        return _OSector(1, nb, (desc.n_sites + desc.two_sz) // 2, 0)
+    return _OSector(1, nb, desc.n_tot, 0)
+
+
+def rows_hv_counted(desc, terms, rows: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """As rows_hv, with targets ranked by counting within desc's sector (no
+    basis list; v holds the whole vector, complex128)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    nvec = 1 if v.ndim == 1 else v.shape[1]
+    if nvec > 64:
+        raise ValueError("nvec <= 64")
+    v = np.ascontiguousarray(v.astype(np.complex128, copy=False))
+    u = np.zeros((len(rows), nvec), dtype=np.complex128)
+    sec = _sector(desc)
+    arr = _terms(terms)
+    rc = lib().oracle_hv_rows_counted(arr, len(terms), C.byref(sec), rows.ctypes.data, len(rows), v.ctypes.data,
+                                      nvec, u.ctypes.data)
+    if rc != 0:
+        raise ValueError("a term leaves the basis")
+    return u if v.ndim == 2 else u[:, 0]
+
+
+def unrank_counted(desc, idx: np.ndarray) -> np.ndarray:
+    """Configurations of the given sector indices (counting, no basis list)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    cfg = np.zeros(len(idx), dtype=np.uint64)
+    sec = _sector(desc)
+    if lib().oracle_unrank_counted(C.byref(sec), idx.ctypes.data, len(idx), cfg.ctypes.data) != 0:
+        raise ValueError("rank out of range")
+    return cfg

@@ -71,6 +71,41 @@ static branch create(int k, branch in) {
     return out;
 }
 
+/* Sector given by counts instead of a list: kind 0 = all bit strings,
+ * 1 = n_a set bits, 2 = n_a set even bits (up) and n_b set odd bits (down). */
+typedef struct {
+    int32_t kind, nbits, n_a, n_b;
+} osector;
+
+static int64_t binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+/* index of t in the ascending list of its sector by counting (Sec. 3.1):
+ * for each set bit, from the top, the sector configurations that agree with t
+ * above it and have a 0 there; -1 if t is not in the sector */
+static int64_t rank_count(uint64_t t, const osector* sec) {
+    if (sec->kind == 0) return (int64_t)t;
+    int na = sec->n_a, nb = sec->n_b;
+    int64_t r = 0;
+    for (int p = sec->nbits - 1; p >= 0; --p) {
+        if (!((t >> p) & 1)) continue;
+        if (sec->kind == 1) {
+            r += binom(p, na);
+            --na;
+        } else {
+            r += binom((p + 1) / 2, na) * binom(p / 2, nb);
+            if (p % 2 == 0) --na; else --nb;
+        }
+    }
+    if (na != 0 || (sec->kind == 2 && nb != 0)) return -1;
+    if (sec->nbits < 64 && (t >> sec->nbits) != 0) return -1;
+    return r;
+}
+
 static int64_t rank_of(uint64_t t, const uint64_t* states, int64_t dim) {
     if (!states) return (int64_t)t;
     int64_t lo = 0, hi = dim - 1;
@@ -140,6 +175,24 @@ static int term_apply(const oterm* T, uint64_t s, branch* out) {
     return n;
 }
 
+/* A term's element <t|T|s> is the sum of all its operator-product branches
+ * that reach t (Sec. 3.3): merge branches with equal targets, so that
+ * branches which cancel (e.g. the S+S+ parts of xx and yy exchange on an Sz
+ * sector) never reach the ranking.  Returns the merged count. */
+static int merge_branches(branch* br, int n) {
+    int m = 0;
+    for (int q = 0; q < n; ++q) {
+        int k = 0;
+        while (k < m && br[k].s != br[q].s) ++k;
+        if (k < m) {
+            br[k].c += br[q].c;
+        } else {
+            br[m++] = br[q];
+        }
+    }
+    return m;
+}
+
 /*
  * u[r*nvec + b] = sum over terms and branches of conj(coef) * v[rank(t)*nvec + b]
  * for the row configurations rows[0..nrows).  v has dim*nvec complex entries.
@@ -155,7 +208,7 @@ int oracle_hv_rows(const oterm* terms, int nterms, const uint64_t* states, int64
         double complex acc[64];
         for (int b = 0; b < nvec; ++b) acc[b] = 0;
         for (int k = 0; k < nterms; ++k) {
-            const int n = term_apply(&terms[k], rows[r], br);
+            const int n = merge_branches(br, term_apply(&terms[k], rows[r], br));
             for (int q = 0; q < n; ++q) {
                 if (br[q].c == 0) continue;
                 const int64_t t = rank_of(br[q].s, states, dim);
@@ -180,7 +233,7 @@ int oracle_hv_rows_c64(const oterm* terms, int nterms, const uint64_t* states, i
         double complex acc[64];
         for (int b = 0; b < nvec; ++b) acc[b] = 0;
         for (int k = 0; k < nterms; ++k) {
-            const int n = term_apply(&terms[k], rows[r], br);
+            const int n = merge_branches(br, term_apply(&terms[k], rows[r], br));
             for (int q = 0; q < n; ++q) {
                 if (br[q].c == 0) continue;
                 const int64_t t = rank_of(br[q].s, states, dim);
@@ -192,6 +245,54 @@ int oracle_hv_rows_c64(const oterm* terms, int nterms, const uint64_t* states, i
         for (int b = 0; b < nvec; ++b) u[r * nvec + b] = acc[b];
     }
     return bad ? -1 : 0;
+}
+
+/* as oracle_hv_rows, targets ranked by counting (no basis list needed) */
+int oracle_hv_rows_counted(const oterm* terms, int nterms, const osector* sec, const uint64_t* rows, int64_t nrows,
+                           const double complex* v, int nvec, double complex* u) {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t r = 0; r < nrows; ++r) {
+        branch br[16];
+        double complex acc[64];
+        for (int b = 0; b < nvec; ++b) acc[b] = 0;
+        for (int k = 0; k < nterms; ++k) {
+            const int n = merge_branches(br, term_apply(&terms[k], rows[r], br));
+            for (int q = 0; q < n; ++q) {
+                if (br[q].c == 0) continue;
+                const int64_t t = rank_count(br[q].s, sec);
+                if (t < 0) { bad = 1; continue; }
+                const double complex cc = conj(br[q].c);
+                for (int b = 0; b < nvec; ++b) acc[b] += cc * v[t * nvec + b];
+            }
+        }
+        for (int b = 0; b < nvec; ++b) u[r * nvec + b] = acc[b];
+    }
+    return bad ? -1 : 0;
+}
+
+/* the configuration of each rank (inverse of rank_count, greedy from the top bit) */
+int oracle_unrank_counted(const osector* sec, const int64_t* idx, int64_t n, uint64_t* cfg) {
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t r = idx[k];
+        if (sec->kind == 0) {
+            cfg[k] = (uint64_t)r;
+            continue;
+        }
+        int na = sec->n_a, nb = sec->n_b;
+        uint64_t s = 0;
+        for (int p = sec->nbits - 1; p >= 0; --p) {
+            const int64_t zero = sec->kind == 1 ? binom(p, na) : binom((p + 1) / 2, na) * binom(p / 2, nb);
+            if (r >= zero) {
+                r -= zero;
+                s |= (uint64_t)1 << p;
+                if (sec->kind == 1 || p % 2 == 0) --na; else --nb;
+            }
+        }
+        if (r != 0) return -1;
+        cfg[k] = s;
+    }
+    return 0;
 }
 
 int oracle_max_threads(void) {

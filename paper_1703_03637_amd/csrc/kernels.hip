@@ -306,7 +306,7 @@ __device__ __forceinline__ void stage_to_lds(void* dst, const void* src, size_t 
 }
 
 // Bytes of LDS the single-pass product stages: the pattern table, and on a
-// sector basis both split rank tables.  Above kLdsStageBytes everything is
+// sector basis the low split rank table.  Above kLdsStageBytes everything is
 // read from global memory instead (GTAB).
 constexpr size_t kLdsStageBytes = 64 * 1024;
 
@@ -342,29 +342,24 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     const BasisDev& bs = A.bs;
     const int n_ops = A.n_ops;
 
-    // pattern table and (sector) rank tables: staged in LDS, or global
+    // pattern table and (sector) low rank table: staged in LDS, or global.
+    // The high rank table is read with scalar loads: every row of a tile
+    // shares its high half, so the target's high half is uniform.
     const double* tab;
-    const int64_t* jhi = nullptr;
     const uint32_t* jlo = nullptr;
+    typedef const __attribute__((address_space(4))) int64_t ConstI64;
+    const ConstI64* jhi = (const ConstI64*)(bs.j_hi);
     if constexpr (GTAB) {
         tab = A.ptab;
-        if constexpr (SECTOR) {
-            jhi = bs.j_hi;
-            jlo = bs.j_lo;
-        }
+        if constexpr (SECTOR) jlo = bs.j_lo;
     } else {
         double* lt = lds_dyn;
         stage_to_lds(lt, A.ptab, size_t(n_ops) * 16 * sizeof(double));
         tab = lt;
         if constexpr (SECTOR) {
-            int64_t* lh = reinterpret_cast<int64_t*>(lt + n_ops * 16);
-            const int n_hi = 1 << (bs.nbits - bs.b_lo);
-            stage_to_lds(lh, bs.j_hi, size_t(n_hi) * 8);
-            // the low table starts on a 16-byte boundary
-            uint32_t* ll = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lh) + ((size_t(n_hi) * 8 + 15) & ~size_t(15)));
+            uint32_t* ll = reinterpret_cast<uint32_t*>(lt + n_ops * 16);
             const int n_lo = 1 << bs.b_lo;
             stage_to_lds(ll, bs.j_lo, size_t(n_lo) * 4);
-            jhi = lh;
             jlo = ll;
         }
         __syncthreads();
@@ -400,14 +395,17 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
         for (int e = 0; e < NE; ++e) g[k][e] = S(0);
 
     for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
-        int64_t k_hi = 0, tile_row0 = 0, cnt = kTile;
+        int64_t k_hi = 0, tile_row0 = 0, cnt = kTile, hrow = 0;
         ST hbits = 0;
+        uint64_t hval = 0;
         uint32_t lobase = 0;
         if constexpr (SECTOR) {
             k_hi = find_high(bs.h_tile, bs.n_high, tile);
             tile_row0 = (tile - bs.h_tile[k_hi]) * kTile;
-            cnt = bs.h_row[k_hi + 1] - bs.h_row[k_hi];
-            hbits = ST(bs.h_val[k_hi] << bs.b_lo);
+            hrow = bs.h_row[k_hi];
+            cnt = bs.h_row[k_hi + 1] - hrow;
+            hval = bs.h_val[k_hi];
+            hbits = ST(hval << bs.b_lo);
             lobase = bs.h_lobase[k_hi];
         }
 #pragma unroll 1
@@ -451,17 +449,26 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                         cr = -cr;
                         ci = -ci;
                     }
-                    const ST t = s ^ ST(xmask);
                     int64_t idx;
+                    bool live = valid;
                     if constexpr (SECTOR) {
-                        // every lookup stays inside its table; a target outside
-                        // the sector only occurs where the element is zero
-                        idx = jhi[t >> bs.b_lo] + int64_t(jlo[t & ST(bs.mask_lo)]);
+                        // target high half (uniform over the tile): its first
+                        // row, or -1 if no row of the sector has it (then every
+                        // element of this operator is zero on this tile)
+                        const uint64_t xm_hi = xmask >> bs.b_lo;
+                        const uint64_t xm_lo = xmask & bs.mask_lo;
+                        const int64_t base_hi = xm_hi ? jhi[hval ^ xm_hi] : hrow;
+                        live = live && base_hi >= 0;
+                        // low part: the row's own rank among its class when the
+                        // operator leaves the low half alone, else the table
+                        const int64_t part_lo =
+                            xm_lo ? int64_t(jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo]) : row - hrow;
+                        idx = base_hi + part_lo;
                     } else {
-                        idx = int64_t(t);
+                        idx = int64_t(s ^ ST(xmask));
                     }
-                    crk[k] = valid ? cr : 0.0;
-                    cik[k] = valid ? ci : 0.0;
+                    crk[k] = live ? cr : 0.0;
+                    cik[k] = live ? ci : 0.0;
                     ik[k] = idx;
                 }
 #pragma unroll
@@ -1148,9 +1155,9 @@ static int make_grid(int occ, const Schedule& sc, int64_t tiles) {
 static size_t hv_stage_bytes(const hphi_ham* H, bool sector) {
     size_t b = size_t(H->n_ops_pad) * 16 * sizeof(double);
     if (sector) {
-        const int b_lo = H->basis->dev.b_lo, b_hi = H->basis->nbits - b_lo;
-        if (b_lo > 20 || b_hi > 20) return kLdsStageBytes + 1;
-        b += (((size_t(1) << b_hi) * 8 + 15) & ~size_t(15)) + (size_t(1) << b_lo) * 4;
+        const int b_lo = H->basis->dev.b_lo;
+        if (b_lo > 20) return kLdsStageBytes + 1;
+        b += (size_t(1) << b_lo) * 4;
     }
     return b;
 }
@@ -1207,8 +1214,8 @@ template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
 static int launch_hv_l(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const bool w64 = L.ham->basis->nbits > 32;
     if (w64) {
-        if constexpr (B <= 2) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
-        return set_error(HPHI_EINVAL, "nvec > 2 needs a space of at most 32 bits");
+        if constexpr (B <= 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
+        return set_error(HPHI_EINVAL, "nvec > 4 needs a space of at most 32 bits");
     }
     if constexpr (B >= 8) {
         switch (sc.lpr) {

@@ -15,6 +15,17 @@ The five production workloads are:
 * ``kagome36_sz0``     Kagome Heisenberg 36 sites PBC, Sz = 0,
                        dim C(36,18) = 9,075,135,300, real FP64 / FP32, seed 5.
 
+Widening beyond them:
+
+* ``hubbard18_tpq``    the paper's 18-site tilted square Hubbard cluster
+                       (a0 = (3, 3), a1 = (-3, 3)), t = 1, U = 8, half filling,
+                       Sz = 0: dim C(18,9)^2 = 2,363,904,400, split 18/18,
+                       microcanonical TPQ, complex128 (one sample) or complex64
+                       (four samples), l = 8.5 (above the largest energy per
+                       site, <= U/2 + 4t), seeds 600...
+* ``hubbard8_tpq``     the paper's 8-site cluster (a0 = (2, 2), a1 = (-2, 2)),
+                       U = 8, half filling, Sz = 0 (dim 4,900), 20 samples.
+
 plus small cases used by tests (4-site ring, two-site Hubbard, ...).
 """
 
@@ -102,6 +113,16 @@ def workload(name: str) -> Workload:
         terms = [L.heisenberg_bond(i, j, 1.0) for (i, j) in L.kagome_bonds(3, 4)]
         return Workload(name, BasisDesc("spin", 36, "sz", two_sz=0, split_bits=18), terms,
                         "f64", "lanczos", n_iter=100, seeds=[5])
+    if name == "hubbard18_tpq":
+        n, bonds, _ = L.square_supercell((3, 3), (-3, 3))
+        terms = L.hubbard_terms(bonds, n, t=1.0, U=8.0)
+        return Workload(name, BasisDesc("fermion", n, "nupndn", n_up=9, n_dn=9, split_bits=18), terms,
+                        "c128", "tpq", n_iter=2000, nvec=1, seeds=[600, 601, 602, 603], tpq_l=8.5)
+    if name == "hubbard8_tpq":
+        n, bonds, _ = L.square_supercell((2, 2), (-2, 2))
+        terms = L.hubbard_terms(bonds, n, t=1.0, U=8.0)
+        return Workload(name, BasisDesc("fermion", n, "nupndn", n_up=4, n_dn=4), terms,
+                        "c128", "tpq", n_iter=400, nvec=16, seeds=list(range(700, 720)), tpq_l=8.5)
     # ---- small cases
     if name == "heis_ring4":
         return Workload(name, BasisDesc("spin", 4), _heis_chain(4), "f64", "lanczos", n_iter=16, seeds=[11])

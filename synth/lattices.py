@@ -212,3 +212,52 @@ def hubbard_terms(bonds, n_sites: int, t: float, U: float) -> List[Term]:
         for i in range(n_sites):
             terms.append(Term(HUBBARD_U, i, -1, (U,)))
     return terms
+
+
+def square_supercell(a0: Tuple[int, int], a1: Tuple[int, int]):
+    """Square-lattice supercell spanned by a0 = a0W e_W + a0L e_L and a1 (the
+    lattice rule of Sec. 2.4 with unit vectors e_W = (1, 0), e_L = (0, 1)).
+
+    Sites: the integer points with fractional coordinates in [0, 1) along
+    (a0, a1), numbered in ascending (y, x).  Bonds: each site to its +x and +y
+    neighbours, folded back by supercell translations; one entry per
+    undirected bond.  Returns (n_sites, bonds, coords).
+    """
+    (ax, ay), (bx, by) = a0, a1
+    det = ax * by - ay * bx
+    if det == 0:
+        raise ValueError("degenerate supercell")
+    sgn = 1 if det > 0 else -1
+    D = abs(det)
+
+    def frac_num(x, y):
+        # numerators of the fractional coordinates (times |det|)
+        return (sgn * (x * by - y * bx), sgn * (ax * y - ay * x))
+
+    xs = [0, ax, bx, ax + bx]
+    ys = [0, ay, by, ay + by]
+    pts = []
+    for y in range(min(ys), max(ys) + 1):
+        for x in range(min(xs), max(xs) + 1):
+            f0, f1 = frac_num(x, y)
+            if 0 <= f0 < D and 0 <= f1 < D:
+                pts.append((x, y))
+    pts.sort(key=lambda p: (p[1], p[0]))
+    index = {p: k for k, p in enumerate(pts)}
+
+    def fold(x, y):
+        f0, f1 = frac_num(x, y)
+        n0, n1 = f0 // D, f1 // D
+        return (x - n0 * ax - n1 * bx, y - n0 * ay - n1 * by)
+
+    bonds = []
+    seen = set()
+    for (x, y) in pts:
+        i = index[(x, y)]
+        for dx, dy in ((1, 0), (0, 1)):
+            j = index[fold(x + dx, y + dy)]
+            key = (min(i, j), max(i, j), dx)
+            if i != j and key not in seen:
+                seen.add(key)
+                bonds.append((i, j))
+    return len(pts), bonds, pts

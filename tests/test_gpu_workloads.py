@@ -90,7 +90,7 @@ def test_w64_small_sectors_match_oracle(name):
         for k in o:
             assert gpu[r][k] == o[k], (r, k)
     H = oh.sparse_h(desc, terms, basis_states=states)
-    for nvec in (1, 2):
+    for nvec in (1, 2, 4):
         v = uniform_vectors(basis.dim, list(range(40, 40 + nvec)), True)
         vd = torch.from_numpy(v).cuda()
         if nvec == 1:
@@ -227,4 +227,77 @@ def test_kagome36_full_size_sampled_rows():
     d = np.abs(u_rows - ref)
     assert np.all(d <= 2.0 ** -24 * np.abs(ref) + 1e-12 * bound + 1e-30)
     del v
+    torch.cuda.empty_cache()
+
+
+def test_hubbard18_full_size_sampled_rows():
+    """The paper's 18-site Hubbard cluster at half filling, Sz = 0 (2,363,904,400 rows, 36-bit
+    interleaved fermion configurations): rank/unrank, element lists (bit-exact) and products on
+    sampled rows -- complex128, and the 4-sample complex64 TPQ step -- against the oracle, which ranks
+    every target by counting (no basis list)."""
+    print("[gpu] hubbard18 full size", flush=True)
+    w = workload("hubbard18_tpq")
+    desc = w.basis
+    basis = hp.hphi_basis_build(desc)
+    dim = basis.dim
+    assert dim == 2363904400
+    ham = hp.hphi_ham_build(basis, w.terms)
+    rng = np.random.default_rng(915)
+    rows = np.unique(np.concatenate([rng.integers(0, dim, 200), [0, 1, dim - 2, dim - 1]]))
+    cfg_ora = np.array([ob.sector_unrank(desc, int(r)) for r in rows], dtype=np.uint64)
+    cfg = hp.hphi_basis_unrank(basis, torch.from_numpy(rows.astype(np.int64)).cuda()).cpu().numpy()
+    assert np.array_equal(cfg.astype(np.uint64), cfg_ora)
+    idx = hp.hphi_basis_rank(basis, torch.from_numpy(cfg_ora.astype(np.int64)).cuda()).cpu().numpy()
+    assert np.array_equal(idx, rows)
+
+    def rank_arr(st):
+        return np.array([ob.sector_rank(desc, int(s)) for s in st], dtype=np.int64)
+
+    for row0 in (0, int(rng.integers(0, dim - 64)), dim - 64):
+        gpu = _elements(ham, row0, 64)
+        st = np.array([ob.sector_unrank(desc, row0 + k) for k in range(64)], dtype=np.uint64)
+        ora = oh.row_elements_sampled(desc, w.terms, st, rank_arr)
+        for k in range(64):
+            o = {kk: complex(vv) for kk, vv in ora[k].items()}
+            assert gpu[k].keys() == o.keys(), (row0, k)
+            for kk in o:
+                assert gpu[k][kk] == o[kk]
+
+    def sampled_check(vec, out, a, b, tol_store):
+        def v_of_state(st):
+            ix = torch.from_numpy(rank_arr(st)).cuda()
+            return vec[ix].cpu().numpy().astype(np.complex128)
+        hv = oh.rows_hv_sampled(desc, w.terms, cfg_ora, v_of_state)
+        vr = v_of_state(cfg_ora)
+        ref = a * hv + b * vr
+        bound = np.zeros(hv.shape)
+        for term in w.terms:
+            for coef, tgt in oh.term_action(term, cfg_ora, desc.particle):
+                nz = np.nonzero(coef != 0)[0]
+                if nz.size:
+                    vals = np.abs(v_of_state(tgt[nz]))
+                    bound[nz] += np.abs(coef[nz])[:, None] * vals if vals.ndim == 2 else np.abs(coef[nz]) * vals
+        got = out[torch.from_numpy(rows.astype(np.int64)).cuda()].cpu().numpy().astype(np.complex128)
+        d = np.abs(got - ref)
+        assert np.all(d <= tol_store * np.abs(ref) + 1e-12 * (abs(a) * bound + abs(b) * np.abs(vr)) + 1e-30)
+
+    # complex128 product, one vector
+    v = device_uniform(dim, 0, 916, True, torch.complex128)
+    u = torch.empty_like(v)
+    hp.hphi_hv(ham, v, u)
+    torch.cuda.synchronize()
+    sampled_check(v, u, 1.0, 0.0, 0.0)
+    del v, u
+    torch.cuda.empty_cache()
+    # batched complex64 TPQ step, four samples
+    ns, l = desc.n_sites, w.tpq_l
+    psi = device_uniform(dim, 4, 917, True, torch.complex64)
+    out = torch.empty_like(psi)
+    obs = torch.empty(16, dtype=torch.float64, device="cuda")
+    hp.hphi_tpq_step(ham, psi, out, l, 1, None, obs)
+    torch.cuda.synchronize()
+    sampled_check(psi, out, -1.0 / ns, l, 2.0 ** -24 * (1 + 1e-6))
+    o = obs.cpu().numpy().reshape(4, 4)
+    assert np.all(np.isfinite(o)) and np.all(np.abs(o[0]) < 8.5)
+    del psi, out
     torch.cuda.empty_cache()

@@ -480,3 +480,53 @@ def test_c_oracle_sector_rows_match_python_oracle():
     v = uniform_vectors(len(st), [6], True)[:, 0]
     u = c_oracle.rows_hv(terms, st, v, states=st)
     assert np.allclose(u, oh.apply_h(desc, terms, v, st), atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("desc", [BasisDesc("fermion", 5, "nupndn", n_up=2, n_dn=3),
+                                  BasisDesc("fermion", 6, "nupndn", n_up=3, n_dn=3),
+                                  BasisDesc("fermion", 6, "nupndn", n_up=1, n_dn=4),
+                                  BasisDesc("fermion", 4, "ntot", n_tot=3),
+                                  BasisDesc("spin", 10, "sz", two_sz=2),
+                                  BasisDesc("spin", 7)])
+def test_sector_rank_by_counting_matches_enumeration(desc):
+    """Counting rank/unrank (no basis list) against the sorted brute-force enumeration."""
+    st = ob.states(desc)
+    assert [ob.sector_rank(desc, int(s)) for s in st] == list(range(len(st)))
+    assert [ob.sector_unrank(desc, i) for i in range(len(st))] == [int(s) for s in st]
+
+
+def test_sector_rank_agrees_with_cns_on_sz_sectors():
+    d = BasisDesc("spin", 36, "sz", two_sz=0)
+    rng = np.random.default_rng(1)
+    for r in rng.integers(0, ob.dimension(d), 50):
+        s = ob.cns_unrank(int(r), 18, 36)
+        assert ob.sector_rank(d, s) == int(r) == ob.cns_rank(s)
+        assert ob.sector_unrank(d, int(r)) == s
+
+
+def test_sector_rank_endpoints_18_site_hubbard():
+    """Half filling on 18 sites: the smallest and largest configurations take the first and last index."""
+    d = BasisDesc("fermion", 18, "nupndn", n_up=9, n_dn=9)
+    lo = sum(1 << (2 * i) for i in range(9)) | sum(1 << (2 * i + 1) for i in range(9))
+    hi = sum(1 << (2 * i) for i in range(9, 18)) | sum(1 << (2 * i + 1) for i in range(9, 18))
+    assert ob.sector_rank(d, lo) == 0 and ob.sector_rank(d, hi) == ob.dimension(d) - 1 == 2363904400 - 1
+    assert ob.sector_unrank(d, 0) == lo and ob.sector_unrank(d, ob.dimension(d) - 1) == hi
+
+
+@pytest.mark.parametrize("desc,terms", [
+    (BasisDesc("fermion", 6, "nupndn", n_up=3, n_dn=2), L.hubbard_terms(L.rect_bonds(3, 2), 6, t=1.0, U=4.0)),
+    (BasisDesc("spin", 10, "sz", two_sz=-2), L.random_spin_terms(10, 12, 31, conserve_sz=True, real=False)),
+    (BasisDesc("fermion", 4, "ntot", n_tot=3), L.random_fermion_terms(4, 8, 32, conserve_spin=False, real=True)),
+])
+def test_c_oracle_counted_rank_matches_list_rank(desc, terms):
+    """The C oracle's counting rank (no basis list) gives the same rows as its list-rank path, and its
+    unrank inverts the enumeration."""
+    from oracle import c_oracle
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), [33, 34], True)
+    a = c_oracle.rows_hv(terms, st, v, states=st)
+    b = c_oracle.rows_hv_counted(desc, terms, st, v)
+    assert np.array_equal(a, b)
+    assert np.array_equal(c_oracle.unrank_counted(desc, np.arange(len(st))), st)
+    ref = oh.sparse_h(desc, terms) @ v
+    assert np.allclose(b, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
