@@ -264,6 +264,21 @@ int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos
                  const void* const* v0, void* const* work, void* const* x_out,
                  hphi_lanczos_result* res, void* stream);
 
+/* ------------------------------------------------------------ observables */
+
+/* Expectation values of a Hermitian observable O in nvec states (Sec. 3.5:
+ * observables of TPQ states and eigenvectors, e.g. the doublon density of
+ * Sec. 5.1).  O is given as a term list built into its own hphi_ham on the
+ * same basis: the Hubbard-U kind with U = 1 counts doublons, a HOP term
+ * measures c+_a c_b + h.c. (2 Re <c+_a c_b>; t = i gives 2 Im), DENS
+ * measures n_a n_b, a spin bond S^a_i S^b_j.  psi: device, dim*nvec
+ * elements of dtype, interleaved as for hphi_hv.  out: device [2 * nvec]
+ * (FP64): out[b] = Re<psi_b|O|psi_b> / <psi_b|psi_b>, out[nvec + b] =
+ * <psi_b|psi_b>.  Uses the product kernels in reduce-only mode (no output
+ * vector) and the reduction workspace of `obs`.  Asynchronous on stream. */
+int hphi_expect(const hphi_ham* obs, const void* psi, int64_t nvec, int32_t dtype, double* out,
+                void* stream);
+
 /* -------------------------------------------------------------------- TPQ */
 
 /* One microcanonical TPQ step (Sec. 3.5) for nvec independent samples:

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     hphi_basis_build,
     hphi_basis_rank,
     hphi_basis_unrank,
+    hphi_expect,
     hphi_ham_build,
     hphi_hv,
     hphi_hv_elements,

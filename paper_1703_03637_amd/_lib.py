@@ -81,6 +81,7 @@ _SIGS = {
                       C.POINTER(LanczosResultC), C.c_void_p], C.c_int),
     "hphi_tpq_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hphi_expect": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_last_error": ([], C.c_char_p),
     "hphi_version": ([], C.c_char_p),
 }

@@ -236,6 +236,16 @@ def hphi_lanczos(hams: Sequence[Ham], v0: Sequence[torch.Tensor], n_iter: int, *
     return out
 
 
+# ------------------------------------------------------------ observables
+
+def hphi_expect(obs: Ham, psi: torch.Tensor) -> torch.Tensor:
+    """<O> per state (FP64 device tensor [nvec]) for the observable `obs` (an Ham built from its terms)."""
+    nv = _nvec(psi, obs.dim)
+    out = torch.empty(2 * nv, dtype=torch.float64, device=psi.device)
+    check(L.lib().hphi_expect(C.c_void_p(obs.handle), _ptr(psi), nv, _dtype_code(psi), _ptr(out), _stream()))
+    return out[:nv]
+
+
 # -------------------------------------------------------------------- TPQ
 
 def hphi_tpq_step(ham: Ham, psi_in: torch.Tensor, psi_out: torch.Tensor, l: float, k: int,

@@ -73,6 +73,28 @@ extern "C" int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows
     return launch_elements(ham, row0, nrows, cap, cols, re, im, term_id, counts, (hipStream_t)stream);
 }
 
+extern "C" int hphi_expect(const hphi_ham* obs, const void* psi, int64_t nvec, int32_t dtype, double* out,
+                           void* stream) {
+    if (!obs || !psi || !out) return set_error(HPHI_EINVAL, "hphi_expect: null argument");
+    if (!valid_nvec(nvec)) return set_error(HPHI_EINVAL, "hphi_expect: nvec must be 1, 2, 4, 8 or 16");
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_expect: bad dtype");
+    if (obs->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_expect: complex observable with real storage");
+    HvLaunch L{};
+    L.ham = obs;
+    L.v = psi;
+    L.u = nullptr;       // reductions only
+    L.a = 1.0;
+    L.b = 0.0;
+    L.nvec = int(nvec);
+    L.dtype = dtype;
+    L.reduce_out = obs->d_red;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = launch_hv(L, st);
+    if (rc) return rc;
+    return launch_expect(obs->d_red, out, int(nvec), st);
+}
+
 extern "C" int hphi_tpq_step(const hphi_ham* ham, const void* psi_in, void* psi_out, int64_t nvec, int32_t dtype,
                              double l, int32_t k, const double* in_scale, double* obs, void* stream) {
     if (!ham || !psi_in || !psi_out || !obs) return set_error(HPHI_EINVAL, "hphi_tpq_step: null argument");

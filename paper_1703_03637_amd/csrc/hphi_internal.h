@@ -189,6 +189,7 @@ int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const do
                           void* acc, const double* ecoef, double* partials, int grid, double* red,
                           const int* stop, hipStream_t st);
 int launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+int launch_expect(const double* red, double* out, int nvec, hipStream_t st);
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k,
                    hipStream_t st);
 

@@ -1032,6 +1032,15 @@ __global__ void fill_zero_kernel(uint32_t* __restrict__ p, int64_t n_words) {
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_words; i += int64_t(gridDim.x) * 256) p[i] = 0u;
 }
 
+// <O> = Re<x|Ox> / <x|x> per vector, and <x|x>
+__global__ void expect_kernel(const double* __restrict__ red, double* __restrict__ out, int nvec) {
+    const int b = threadIdx.x;
+    if (b >= nvec) return;
+    const double xx = red[0 * nvec + b], xo = red[1 * nvec + b];
+    out[b] = xo / xx;
+    out[nvec + b] = xx;
+}
+
 __global__ void tpq_obs_kernel(const double* __restrict__ red, double* __restrict__ obs, int nvec, double ns,
                                double l, int k) {
     const int b = threadIdx.x;
@@ -1432,6 +1441,11 @@ int launch_fill_zero(void* p, int64_t bytes, hipStream_t st) {
     const int64_t words = bytes / 4;
     fill_zero_kernel<<<stream_grid(words), 256, 0, st>>>((uint32_t*)p, words);
     return check_hip(hipGetLastError(), "fill_zero launch");
+}
+
+int launch_expect(const double* red, double* out, int nvec, hipStream_t st) {
+    expect_kernel<<<1, 64, 0, st>>>(red, out, nvec);
+    return check_hip(hipGetLastError(), "expect launch");
 }
 
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k, hipStream_t st) {
