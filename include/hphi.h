@@ -55,7 +55,8 @@ enum {
     HPHI_EDEVICE = -3,      /* HIP runtime error (message in hphi_last_error)      */
     HPHI_ESECTOR = -4,      /* a term maps a sector state outside the sector       */
     HPHI_EDTYPE = -5,       /* complex matrix elements with a real storage type    */
-    HPHI_INFO_BREAKDOWN = 1 /* Lanczos stopped early: beta below tolerance or dim  */
+    HPHI_INFO_BREAKDOWN = 1, /* Lanczos stopped early: beta below tolerance or dim */
+    HPHI_INFO_MAXITER = 2    /* a CG solve reached its iteration limit             */
 };
 
 enum { HPHI_SPIN_HALF = 0, HPHI_FERMION = 1 };
@@ -263,6 +264,37 @@ typedef struct {
 int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos_opts* opts,
                  const void* const* v0, void* const* work, void* const* x_out,
                  hphi_lanczos_result* res, void* stream);
+
+/* Inverse-iteration refinement of an eigenvector (Sec. 3.4, inverse
+ * iteration method; App. A.3): starting from y_0 = x (the Lanczos
+ * eigenvector), n_inverse times solve (H - E') y_{k+1} = y_k by conjugate
+ * gradients, starting each solve from y_k, and normalize; E' = e_approx +
+ * shift, the small positive shift that stabilizes CG.  All FP64.
+ *   x      device, dim elements of dtype F64 or C128 (the x_out of
+ *          hphi_lanczos); in: approximate eigenvector, out: refined, |x| = 1
+ *   work   device scratch of 3 * dim elements of dtype (r, p, q: with x the
+ *          four vectors of the method)
+ *   res    host: E = <x|H|x>, variance, residual |Hx - Ex| of the result, the
+ *          CG iterations taken, info = HPHI_OK or HPHI_INFO_MAXITER
+ * opts NULL = {1e-6, 2, 1000, 1e-12}.  Synchronizes `stream` (each CG step
+ * reads its two FP64 scalars on the host). */
+typedef struct {
+    double shift;         /* added to e_approx (> 0)                            */
+    int32_t n_inverse;    /* inverse-iteration steps (>= 1)                     */
+    int32_t cg_max_iter;  /* per solve                                          */
+    double cg_tol;        /* stop when |r| <= cg_tol |y_k| (|y_k| = 1)          */
+} hphi_cg_opts;
+
+typedef struct {
+    double e_refined;
+    double variance;
+    double residual;
+    int32_t cg_iters;
+    int32_t info;
+} hphi_cg_result;
+
+int hphi_cg_refine(const hphi_ham* ham, void* x, int32_t dtype, double e_approx, const hphi_cg_opts* opts,
+                   void* work, hphi_cg_result* res, void* stream);
 
 /* ------------------------------------------------------------ observables */
 

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     hphi_basis_build,
     hphi_basis_rank,
     hphi_basis_unrank,
+    hphi_cg_refine,
     hphi_expect,
     hphi_ham_build,
     hphi_hv,

@@ -20,6 +20,7 @@ HPHI_EDEVICE = -3
 HPHI_ESECTOR = -4
 HPHI_EDTYPE = -5
 HPHI_INFO_BREAKDOWN = 1
+HPHI_INFO_MAXITER = 2
 
 HPHI_SPIN_HALF, HPHI_FERMION = 0, 1
 HPHI_SECTOR_NONE, HPHI_SECTOR_SZ, HPHI_SECTOR_NUP_NDN, HPHI_SECTOR_NTOT = 0, 1, 2, 3
@@ -54,6 +55,15 @@ class LanczosResultC(C.Structure):
                 ("e0_refined", C.c_double), ("variance", C.c_double), ("residual", C.c_double)]
 
 
+class CgOptsC(C.Structure):
+    _fields_ = [("shift", C.c_double), ("n_inverse", C.c_int32), ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double)]
+
+
+class CgResultC(C.Structure):
+    _fields_ = [("e_refined", C.c_double), ("variance", C.c_double), ("residual", C.c_double),
+                ("cg_iters", C.c_int32), ("info", C.c_int32)]
+
+
 class HphiError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"hphi error {code}: {msg}")
@@ -81,6 +91,8 @@ _SIGS = {
                       C.POINTER(LanczosResultC), C.c_void_p], C.c_int),
     "hphi_tpq_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hphi_cg_refine": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(CgOptsC), C.c_void_p,
+                        C.POINTER(CgResultC), C.c_void_p], C.c_int),
     "hphi_expect": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_last_error": ([], C.c_char_p),
     "hphi_version": ([], C.c_char_p),

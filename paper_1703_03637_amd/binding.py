@@ -236,6 +236,22 @@ def hphi_lanczos(hams: Sequence[Ham], v0: Sequence[torch.Tensor], n_iter: int, *
     return out
 
 
+def hphi_cg_refine(ham: Ham, x: torch.Tensor, e_approx: float, *, shift: float = 1e-6, n_inverse: int = 2,
+                   cg_max_iter: int = 1000, cg_tol: float = 1e-12, work=None) -> dict:
+    """Inverse-iteration refinement of the FP64 eigenvector x in place (CG solves); returns E, variance,
+    residual, CG iterations and info."""
+    if x.dtype not in (torch.float64, torch.complex128) or _nvec(x, ham.dim) != 1:
+        raise ValueError("x must be a 1-D float64 or complex128 vector")
+    if work is None:
+        work = torch.empty(3 * ham.dim, dtype=x.dtype, device=x.device)
+    opts = L.CgOptsC(shift, n_inverse, cg_max_iter, cg_tol)
+    res = L.CgResultC()
+    check(L.lib().hphi_cg_refine(C.c_void_p(ham.handle), _ptr(x), _dtype_code(x), float(e_approx), C.byref(opts),
+                                 _ptr(work), C.byref(res), _stream()), allow=(L.HPHI_OK,))
+    return dict(e_refined=res.e_refined, variance=res.variance, residual=res.residual, cg_iters=res.cg_iters,
+                info=res.info)
+
+
 # ------------------------------------------------------------ observables
 
 def hphi_expect(obs: Ham, psi: torch.Tensor) -> torch.Tensor:

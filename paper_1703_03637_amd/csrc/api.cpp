@@ -556,3 +556,99 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
     }
     return HPHI_OK;
 }
+
+extern "C" int hphi_cg_refine(const hphi_ham* ham, void* x, int32_t dtype, double e_approx,
+                              const hphi_cg_opts* opts, void* work, hphi_cg_result* res, void* stream) {
+    if (!ham || !x || !work || !res) return set_error(HPHI_EINVAL, "hphi_cg_refine: null argument");
+    if (dtype != HPHI_F64 && dtype != HPHI_C128)
+        return set_error(HPHI_EINVAL, "hphi_cg_refine: the vector must be FP64 (F64 or C128)");
+    if (ham->is_complex && dtype != HPHI_C128)
+        return set_error(HPHI_EDTYPE, "hphi_cg_refine: complex Hamiltonian with real storage");
+    const hphi_cg_opts o = opts ? *opts : hphi_cg_opts{1e-6, 2, 1000, 1e-12};
+    if (!(o.shift > 0) || !std::isfinite(o.shift) || o.n_inverse < 1 || o.cg_max_iter < 1 || !(o.cg_tol > 0) ||
+        !std::isfinite(e_approx))
+        return set_error(HPHI_EINVAL, "hphi_cg_refine: bad options");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t dim = ham->basis->dim;
+    const int64_t n = dim * (dtype == HPHI_C128 ? 2 : 1);   // FP64 scalars per vector
+    double* X = static_cast<double*>(x);
+    double* R = static_cast<double*>(work);
+    double* P = R + n;
+    double* Q = P + n;
+    double* mem = nullptr;
+    if (hipMalloc(&mem, (2048 + 64) * sizeof(double)) != hipSuccess)
+        return set_error(HPHI_ENOMEM, "hphi_cg_refine: workspace");
+    double* partials = mem;
+    double* red = mem + 2048;                // [0..3] product sums, [8] a norm
+    const double Ep = e_approx + o.shift;
+    int rc = HPHI_OK;
+    res->cg_iters = 0;
+    res->info = HPHI_OK;
+    auto host = [&](double* dst, const double* src, int cnt) {
+        int r = check_hip(hipMemcpyAsync(dst, src, size_t(cnt) * 8, hipMemcpyDeviceToHost, st), "copy scalar");
+        return r ? r : check_hip(hipStreamSynchronize(st), "cg sync");
+    };
+    // A v = (H - E') v in one product call: a = 1, b = -E'
+    auto apply = [&](const double* v, double* u, double* pap) {
+        HvLaunch L{};
+        L.ham = ham;
+        L.v = v;
+        L.u = u;
+        L.a = 1.0;
+        L.b = -Ep;
+        L.nvec = 1;
+        L.dtype = dtype;
+        L.reduce_out = red;
+        int r = launch_hv(L, st);
+        double q[2];
+        if (!r) r = host(q, red, 2);
+        if (!r) *pap = q[1] - Ep * q[0];     // <v|Hv> - E' <v|v>
+        return r;
+    };
+    for (int it = 0; it < o.n_inverse && !rc; ++it) {
+        // CG for A y = b with b = y_k (|b| = 1) from x_0 = y_k: r = b - A b
+        double pap = 0.0, rr = 0.0;
+        rc = apply(X, Q, &pap);
+        if (!rc) rc = launch_lincomb(R, X, Q, n, 1.0, -1.0, partials, red + 8, st);
+        if (!rc) rc = host(&rr, red + 8, 1);
+        if (!rc) rc = launch_lincomb(P, R, R, n, 1.0, 0.0, partials, nullptr, st);
+        int j = 0;
+        bool done = std::sqrt(rr) <= o.cg_tol;
+        for (; !rc && !done && j < o.cg_max_iter; ++j) {
+            rc = apply(P, Q, &pap);
+            if (rc) break;
+            if (!std::isfinite(pap) || pap == 0.0) break;    // breakdown: keep the current iterate
+            const double alpha = rr / pap;
+            rc = launch_lincomb(X, X, P, n, 1.0, alpha, partials, nullptr, st);
+            double rn = 0.0;
+            if (!rc) rc = launch_lincomb(R, R, Q, n, 1.0, -alpha, partials, red + 8, st);
+            if (!rc) rc = host(&rn, red + 8, 1);
+            if (rc) break;
+            if (std::sqrt(rn) <= o.cg_tol) {
+                done = true;
+                ++j;
+                break;
+            }
+            rc = launch_lincomb(P, R, P, n, 1.0, rn / rr, partials, nullptr, st);
+            rr = rn;
+        }
+        res->cg_iters += j;
+        if (!rc && !done && j >= o.cg_max_iter) res->info = HPHI_INFO_MAXITER;
+        // normalize y_{k+1}
+        double xx = 0.0;
+        if (!rc) rc = launch_lincomb(X, X, X, n, 1.0, 0.0, partials, red + 8, st);
+        if (!rc) rc = host(&xx, red + 8, 1);
+        if (!rc && !(xx > 0.0 && std::isfinite(xx))) rc = set_error(HPHI_EDEVICE, "hphi_cg_refine: vector vanished");
+        if (!rc) rc = launch_lincomb(X, X, X, n, 1.0 / std::sqrt(xx), 0.0, partials, nullptr, st);
+    }
+    if (!rc) {
+        hphi_lanczos_result lr{};
+        rc = refine_one(ham, X, dtype, red, lr, st);
+        res->e_refined = lr.e0_refined;
+        res->variance = lr.variance;
+        res->residual = lr.residual;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    return rc;
+}

@@ -189,6 +189,9 @@ int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const do
                           void* acc, const double* ecoef, double* partials, int grid, double* red,
                           const int* stop, hipStream_t st);
 int launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
+// w = a x + b y (FP64, n scalars; w may alias x or y); |w|^2 into *norm2 if non-null
+int launch_lincomb(double* w, const double* x, const double* y, int64_t n, double a, double b, double* partials,
+                   double* norm2, hipStream_t st);
 int launch_expect(const double* red, double* out, int nvec, hipStream_t st);
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k,
                    hipStream_t st);

@@ -1028,6 +1028,25 @@ __global__ __launch_bounds__(256) void lanczos_update_multi_kernel(const UpdDesc
                    int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
 }
 
+// w = a x + b y over n FP64 scalars (w may alias x or y), |w|^2 partials per block
+__global__ __launch_bounds__(256) void lincomb_kernel(double* w, const double* x, const double* y, int64_t n,
+                                                      double a, double b, double* __restrict__ partials) {
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const double v = a * x[i] + b * y[i];
+        w[i] = v;
+        s += v * v;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (int(threadIdx.x) < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
 __global__ void fill_zero_kernel(uint32_t* __restrict__ p, int64_t n_words) {
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_words; i += int64_t(gridDim.x) * 256) p[i] = 0u;
 }
@@ -1434,6 +1453,16 @@ int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const do
     int rc = check_hip(hipGetLastError(), "lanczos_update launch");
     if (rc) return rc;
     reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, red, stop);
+    return check_hip(hipGetLastError(), "reduce launch");
+}
+
+int launch_lincomb(double* w, const double* x, const double* y, int64_t n, double a, double b, double* partials,
+                   double* norm2, hipStream_t st) {
+    const int grid = stream_grid(n);
+    lincomb_kernel<<<grid, 256, 0, st>>>(w, x, y, n, a, b, partials);
+    int rc = check_hip(hipGetLastError(), "lincomb launch");
+    if (rc || !norm2) return rc;
+    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, norm2, nullptr);
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
