@@ -133,9 +133,12 @@ def measured_traffic(sched):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="kh_honeycomb24", choices=("kh_honeycomb24", "hubbard18"),
+    ap.add_argument("--workload", default="kh_honeycomb24",
+                    choices=("kh_honeycomb24", "hubbard18", "heis_chain16", "hubbard_4x3", "tri24"),
                     help="kh_honeycomb24: the headline (24-site Kitaev-Heisenberg TPQ, 16 complex64 samples); "
-                         "hubbard18: the paper's 18-site Hubbard cluster at half filling (2,363,904,400 rows)")
+                         "hubbard18: the paper's 18-site Hubbard cluster at half filling (2,363,904,400 rows); "
+                         "heis_chain16 / hubbard_4x3: FP64 Lanczos; tri24: the 13 Sz sectors of the 24-site "
+                         "triangular torus as one batched FP32 Lanczos")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 5 for hubbard18)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3; 1 for hubbard18)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -147,10 +150,11 @@ def main():
                          "[,stage_tables]' for both paths instead of autotuning (used for profiling runs)")
     args = ap.parse_args()
     big = args.workload == "hubbard18"
+    lanczos_mode = args.workload in ("heis_chain16", "hubbard_4x3", "tri24")
     if args.steps is None:
-        args.steps = 5 if big else 20
+        args.steps = 5 if big else (200 if lanczos_mode else 20)
     if args.warmup is None:
-        args.warmup = 1 if big else 3
+        args.warmup = 1 if big else (20 if lanczos_mode else 3)
     if args.schedule:
         keys = ("HPHI_WINDOWED", "HPHI_L2_WINDOW_KB", "HPHI_PASSES", "HPHI_LPR", "HPHI_BLOCKS_PER_CU",
                 "HPHI_STAGE_TABLES")
@@ -176,6 +180,9 @@ def main():
     from synth.vectors import device_uniform
     if big:
         run_hubbard18(args, hp, torch, np)
+        return
+    if lanczos_mode:
+        run_lanczos(args, hp, torch, np)
         return
 
     w = workload("kh_honeycomb24")
@@ -268,6 +275,96 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, w.terms, v_host, dim, nvec)
         res["cpu_baseline"]["host"] = {"nproc": os.cpu_count()}
     print(json.dumps(res), flush=True)
+
+
+def run_lanczos(args, hp, torch, np):
+    """Lanczos workloads: one step = one iteration of every problem's
+    recurrence (product with the fused alpha sums, update with the fused
+    norm, device-side scalars, graph replays).  value = products per second
+    over all problems; roofline = the product on the largest problem timed
+    alone with HIP events; the FP64 refinement reported per problem."""
+    from synth.configs import workload
+    from synth.vectors import device_uniform
+    name = args.workload
+    w = workload("tri24_allsz" if name == "tri24" else name)
+    descs = [w.basis] + list(w.extra_bases)
+    dt = {"c128": torch.complex128, "f32": torch.float32, "f64": torch.float64, "c64": torch.complex64}[w.dtype]
+    cplx = dt.is_complex
+    bases = [hp.hphi_basis_build(d) for d in descs]
+    hams = [hp.hphi_ham_build(b, w.terms) for b in bases]
+    x0 = [device_uniform(b.dim, 0, w.seeds[k % len(w.seeds)], cplx, dt) for k, b in enumerate(bases)]
+    hp.hphi_lanczos(hams, x0, args.warmup, refine=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = hp.hphi_lanczos(hams, x0, args.steps, refine=False)
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    products = sum(r["n_done"] for r in res)
+    steps_done = max(r["n_done"] for r in res)
+    ms_step = dt_s * 1e3 / steps_done
+    ref = hp.hphi_lanczos(hams, x0, args.steps, refine=True)
+    # dominant kernel: the product on the largest problem, alone, HIP events
+    big = max(range(len(bases)), key=lambda k: bases[k].dim)
+    v = x0[big]
+    u = torch.empty_like(v)
+    hp.hphi_hv(hams[big], v, u)
+    torch.cuda.synchronize()
+    k_ms = _events_ms(lambda: hp.hphi_hv(hams[big], v, u), max(5, args.kernel_reps), torch)
+    esize = v.element_size()
+    alg_bytes = bases[big].dim * esize * 2
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    # per step: product reads v_k and v_{k-1}, writes w; update reads w and v_k, writes w
+    step_bytes = sum(b.dim for b in bases) * esize * 6
+    out = {
+        "metric": METRIC,
+        "value": products / dt_s,
+        "unit": "H·v products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{name}_lanczos_{w.dtype}", "problems": len(bases),
+                   "dims": [b.dim for b in bases], "n_terms": len(w.terms), "iterations": args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"one product on the largest problem (dim {bases[big].dim})", "kernel_ms": k_ms,
+                     "algorithmic_bytes": alg_bytes},
+        "step_gbps": step_bytes / (ms_step * 1e-3) / 1e9,
+        "refined": [{"dim": b.dim, "e0_ritz": r["e0_ritz"], "e0_refined": r["e0_refined"],
+                     "residual": r["residual"]} for b, r in list(zip(bases, ref))[:4]],
+    }
+    if not args.no_cpu:
+        from oracle import c_oracle
+        d = descs[big]
+        vh = v.cpu().numpy().astype(np.complex128)
+        rows_n = 4096
+        while True:
+            cfg = c_oracle.unrank_counted(d, np.arange(min(rows_n, bases[big].dim)))
+            t0 = time.perf_counter()
+            c_oracle.rows_hv_counted(d, w.terms, cfg, vh)
+            dtc = time.perf_counter() - t0
+            if dtc >= 10.0 or rows_n >= bases[big].dim:
+                break
+            rows_n = int(min(bases[big].dim, rows_n * min(50.0, 12.0 / max(dtc, 1e-3))))
+        n_rows = len(cfg)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            c_oracle.rows_hv_counted(d, w.terms, cfg, vh)
+            reps += 1
+            dtc = time.perf_counter() - t0
+            if n_rows < bases[big].dim or dtc >= 10.0:
+                break
+        out["cpu_baseline"] = {"value": reps * (n_rows / bases[big].dim) / dtc, "unit": "H·v products/s",
+                               "cores": c_oracle.threads(), "kind": "oracle",
+                               "sample": f"C oracle (hv_oracle.c, OpenMP, counting ranks), {reps} x rows "
+                                         f"0..{n_rows - 1} of the largest problem ({bases[big].dim} rows), "
+                                         f"{dtc:.1f} s"}
+    print(json.dumps(out), flush=True)
 
 
 def run_hubbard18(args, hp, torch, np):
