@@ -255,6 +255,12 @@ typedef struct {
  * recurrence is replayed bit-for-bit to accumulate x = sum_k e~_k v_k in
  * FP64 (App. A.3) and E, variance and residual are measured with an FP64
  * product.
+ * Several problems (n_hams > 1, up to 64) that share the coefficient type,
+ * the space kind (sector or full) and the configuration width run as one
+ * batched recurrence: each step is one persistent product launch, one
+ * update launch and one scalar launch for all of them (uneven sizes split
+ * the grid in proportion to their tiles), each odd/even step pair replayed
+ * from one captured graph; other combinations run one problem at a time.
  *   hams[n_hams]  one Hamiltonian per independent problem (e.g. Sz sectors)
  *   v0[h]         device start vector, storage dtype, dim_h entries
  *   work[h]       device scratch of 2 * dim_h storage elements

@@ -208,23 +208,19 @@ __device__ __forceinline__ uint32_t parity_masked(typename StateT<W64>::type s, 
     }
 }
 
-// Reduce one quantity over the rows held by a wavefront.  Each lane holds
-// VPL per-row values (its share of the vectors); afterwards lane L holds the
-// wave sum for the local vector L >> (6 - log2 VPL) of share L & (LPR-1)
-// (vec_lane maps a vector to its share and local index).  The
-// first log2(VPL) exchange steps run in the storage precision (at most VPL
-// <= 16 products summed), the remaining steps and everything after in FP64.
 // branch-free choice between two values by a lane mask (all ones / zero):
 // a bitwise select, so no register array is ever indexed per lane
-__device__ __forceinline__ float pick(uint32_t m, float a, float b) {
-    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
-}
 __device__ __forceinline__ double pick(uint32_t m, double a, double b) {
     const uint64_t mm = (uint64_t(m) << 32) | m;
     const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
     return __longlong_as_double(static_cast<long long>((ua & mm) | (ub & ~mm)));
 }
 
+// Reduce one quantity over the rows held by a wavefront.  Each lane holds
+// VPL per-row values (its share of the vectors); afterwards lane L holds the
+// wave sum for the local vector L >> (6 - log2 VPL) of share L & (LPR-1)
+// (vec_lane maps a vector to its share and local index).  Every step is
+// FP64.
 template <typename R, int VPL, int LPR>
 __device__ __forceinline__ double wave_reduce_rows(R (&x)[VPL], int lane) {
     constexpr int LOGV = Log2<VPL>::value;
@@ -938,9 +934,9 @@ __global__ void rank_kernel(BasisDev bs, int32_t particle, int32_t sector, int32
     }
     bool ok = true;
     if (sector == HPHI_SECTOR_SZ || sector == HPHI_SECTOR_NTOT) {
-        ok = __popcll(c) == ta;
+        ok = int(__popcll(c)) == ta;
     } else if (sector == HPHI_SECTOR_NUP_NDN) {
-        ok = __popcll(c & 0x5555555555555555ull) == ta && __popcll(c & 0xAAAAAAAAAAAAAAAAull) == tb;
+        ok = int(__popcll(c & 0x5555555555555555ull)) == ta && int(__popcll(c & 0xAAAAAAAAAAAAAAAAull)) == tb;
     }
     (void)particle;
     if (!ok) {
