@@ -109,9 +109,9 @@ def kernel_source_hash() -> str:
 def schedule_key(sched) -> str:
     if isinstance(sched, dict) and "pinned" in sched:
         parts = sched["pinned"].split(",")
-        return ",".join(parts + ["1"] * (6 - len(parts)))
+        return ",".join(parts + ["1", "1"][len(parts) - 5:] if len(parts) < 7 else parts)
     return ",".join(str(sched[k]) for k in ("windowed", "window_kb", "max_passes", "lanes_per_row",
-                                            "blocks_per_cu", "stage_tables"))
+                                            "blocks_per_cu", "stage_tables", "nt_streams"))
 
 
 def measured_traffic(sched):
@@ -147,7 +147,8 @@ def main():
                     help="only run three 1 GiB device copies (reference kernel for the PMC byte counters) and exit")
     ap.add_argument("--schedule", default="",
                     help="pin the product schedule 'windowed,window_kb,max_passes,lanes_per_row,blocks_per_cu"
-                         "[,stage_tables]' for both paths instead of autotuning (used for profiling runs)")
+                         "[,stage_tables[,nt_streams]]' for both paths instead of autotuning (used for profiling "
+                         "runs)")
     args = ap.parse_args()
     big = args.workload == "hubbard18"
     lanczos_mode = args.workload in ("heis_chain16", "hubbard_4x3", "tri24")
@@ -157,7 +158,7 @@ def main():
         args.warmup = 1 if big else (20 if lanczos_mode else 3)
     if args.schedule:
         keys = ("HPHI_WINDOWED", "HPHI_L2_WINDOW_KB", "HPHI_PASSES", "HPHI_LPR", "HPHI_BLOCKS_PER_CU",
-                "HPHI_STAGE_TABLES")
+                "HPHI_STAGE_TABLES", "HPHI_NT_STREAMS")
         for k, val in zip(keys, args.schedule.split(",")):
             os.environ[k] = val
     if args.gpus != 1:

@@ -201,11 +201,13 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different
  * schedule may change the last bits of the reductions.  sched_out (host,
- * may be NULL) receives 7 ints: windowed (0: single pass, 1: windowed,
+ * may be NULL) receives 8 ints: windowed (0: single pass, 1: windowed,
  * 2: windowed with staged copies), window_kb, max_passes,
  * lanes_per_row, blocks_per_cu, stage_tables (single-pass kernel: 1 =
  * pattern and rank tables staged in LDS when they fit, 0 = read from
- * global memory), microseconds per product call.  If the
+ * global memory), nt_streams (windowed kernel, nvec >= 8: 1 = partial
+ * sums, output and staged copies move with non-temporal hints so they do
+ * not evict the gather window from L2), microseconds per product call.  If the
  * environment variable HPHI_TUNE_CACHE names a file, the choice is
  * appended there and reused by later processes for the same device,
  * space and operators.  Synchronizes `stream`. */

@@ -180,9 +180,10 @@ def hphi_hv_tune(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None) ->
     nv = _nvec(v, ham.dim)
     if u is None:
         u = torch.empty_like(v)
-    out = (C.c_int32 * 7)()
+    out = (C.c_int32 * 8)()
     check(L.lib().hphi_hv_tune(C.c_void_p(ham.handle), _ptr(v), _ptr(u), nv, _dtype_code(v), out, _stream()))
-    keys = ("windowed", "window_kb", "max_passes", "lanes_per_row", "blocks_per_cu", "stage_tables", "us")
+    keys = ("windowed", "window_kb", "max_passes", "lanes_per_row", "blocks_per_cu", "stage_tables", "nt_streams",
+            "us")
     return dict(zip(keys, list(out)))
 
 

@@ -53,6 +53,7 @@ struct Schedule {
     int lpr = 0;            // lanes per row (nvec >= 8); 0 = default
     int blocks_per_cu = 0;  // resident blocks per CU; 0 = as many as fit
     int stage_tables = 1;   // single-pass kernel: stage pattern and rank tables in LDS when they fit
+    int nt_streams = 0;     // windowed kernel: non-temporal hints on partial sums, output and staged copies
 };
 
 // Compact kernel-side operator of the windowed product (configurations of

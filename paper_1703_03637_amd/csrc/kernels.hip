@@ -126,6 +126,60 @@ __device__ __forceinline__ void put_chunk(char* dst, const char* src) {
     }
 }
 
+// streaming variants: non-temporal hint (data not reused, should not evict
+// the L2 window of the gathers)
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+template <int CB>
+__device__ __forceinline__ void copy_chunk_nt(char* dst, const char* src) {
+    if constexpr (CB == 16) {
+        const u32x4_t w = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(src));
+        __builtin_memcpy(dst, &w, 16);
+    } else if constexpr (CB == 8) {
+        const u32x2_t w = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t*>(src));
+        __builtin_memcpy(dst, &w, 8);
+    } else {
+        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(src));
+        __builtin_memcpy(dst, &w, 4);
+    }
+}
+
+template <int CB>
+__device__ __forceinline__ void put_chunk_nt(char* dst, const char* src) {
+    if constexpr (CB == 16) {
+        u32x4_t w;
+        __builtin_memcpy(&w, src, 16);
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4_t*>(dst));
+    } else if constexpr (CB == 8) {
+        u32x2_t w;
+        __builtin_memcpy(&w, src, 8);
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x2_t*>(dst));
+    } else {
+        uint32_t w;
+        __builtin_memcpy(&w, src, 4);
+        __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(dst));
+    }
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void load_lane_nt(const S* __restrict__ base, int64_t row, int sub, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    const char* p = reinterpret_cast<const char*>(base) + row * Ly::RB + sub * Ly::CB;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk_nt<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, p + j * LPR * Ly::CB);
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void store_lane_nt(S* __restrict__ base, int64_t row, int sub, const S (&in)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    char* p = reinterpret_cast<char*>(base) + row * Ly::RB + sub * Ly::CB;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        put_chunk_nt<Ly::CB>(p + j * LPR * Ly::CB, reinterpret_cast<const char*>(in) + j * Ly::CB);
+}
+
 template <typename S, int NE, int LPR>
 __device__ __forceinline__ void load_lane(const S* __restrict__ base, int64_t row, int sub, S (&out)[NE]) {
     using Ly = LaneLayout<S, NE, LPR>;
@@ -614,7 +668,7 @@ struct HvwArgs {
     double* partials;
 };
 
-template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT>
 __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     constexpr int NC = CPLX ? 2 : 1;
     constexpr int VPL = B / LPR;
@@ -768,12 +822,16 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
 
             alignas(16) S vr[NE];
             load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
-            if (stg) store_lane<S, NE, LPR>(stg, int64_t(qn), sub, vr);
+            if (stg) {
+                if constexpr (NT) store_lane_nt<S, NE, LPR>(stg, int64_t(qn), sub, vr);
+                else store_lane<S, NE, LPR>(stg, int64_t(qn), sub, vr);
+            }
 #pragma unroll
             for (int e = 0; e < NE; ++e) acc[e] += dsum * double(vr[e]);   // raw (unscaled) H v of this pass
             if (!first) {
                 alignas(16) S pr[NE];
-                load_lane<S, NE, LPR>(u, row, sub, pr);
+                if constexpr (NT) load_lane_nt<S, NE, LPR>(u, row, sub, pr);
+                else load_lane<S, NE, LPR>(u, row, sub, pr);
 #pragma unroll
                 for (int e = 0; e < NE; ++e) acc[e] += double(pr[e]);
             }
@@ -781,7 +839,8 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 alignas(16) S ps[NE];
 #pragma unroll
                 for (int e = 0; e < NE; ++e) ps[e] = S(acc[e]);
-                store_lane<S, NE, LPR>(u, row, sub, ps);
+                if constexpr (NT) store_lane_nt<S, NE, LPR>(u, row, sub, ps);
+                else store_lane<S, NE, LPR>(u, row, sub, ps);
                 continue;
             }
             double ur[NE], xr[NE];
@@ -816,7 +875,8 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 alignas(16) S us[NE];
 #pragma unroll
                 for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
-                store_lane<S, NE, LPR>(u, row, sub, us);
+                if constexpr (NT) store_lane_nt<S, NE, LPR>(u, row, sub, us);
+                else store_lane<S, NE, LPR>(u, row, sub, us);
             }
             wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
         }
@@ -1264,11 +1324,11 @@ static int launch_hv_b(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
 }
 
 // ---- windowed full-space launches
-template <typename S, bool CPLX, bool CCOEF, int B, int LPR>
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT>
 static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
                         hipStream_t st) {
     const hphi_ham* H = L.ham;
-    static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR>);
+    static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR, NT>);
     const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
     HvwArgs A;
     A.nbits = H->basis->nbits;
@@ -1296,7 +1356,7 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
         A.stage = next ? stage[p & 1] : nullptr;
         A.inv_next = next ? P->d_inv + size_t(p + 1) * 64 : nullptr;
         const size_t lds = size_t(A.kop_end - A.kop_begin) * 4 * (CCOEF ? 4 : 2) * sizeof(double);
-        hvw_kernel<S, CPLX, CCOEF, B, LPR><<<grid, kBlock, lds, st>>>(A);
+        hvw_kernel<S, CPLX, CCOEF, B, LPR, NT><<<grid, kBlock, lds, st>>>(A);
         int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
         if (rc) return rc;
     }
@@ -1311,13 +1371,20 @@ template <typename S, bool CPLX, bool CCOEF, int B>
 static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
                         hipStream_t st) {
     if constexpr (B >= 8) {
+        if (sc.nt_streams) {
+            switch (sc.lpr) {
+                case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, true>(L, P, sc, staged, stage, st);
+                case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, true>(L, P, sc, staged, stage, st);
+                case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, true>(L, P, sc, staged, stage, st);
+            }
+        }
         switch (sc.lpr) {
-            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2>(L, P, sc, staged, stage, st);
-            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4>(L, P, sc, staged, stage, st);
-            case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8>(L, P, sc, staged, stage, st);
+            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, false>(L, P, sc, staged, stage, st);
+            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, false>(L, P, sc, staged, stage, st);
+            case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, false>(L, P, sc, staged, stage, st);
         }
     }
-    return launch_hvw_t<S, CPLX, CCOEF, B, 1>(L, P, sc, staged, stage, st);
+    return launch_hvw_t<S, CPLX, CCOEF, B, 1, false>(L, P, sc, staged, stage, st);
 }
 
 // windowed product when it applies (full space, <= 32 bits, no in-place

@@ -4,7 +4,8 @@
 // The tuner times candidate schedules of the real product on the caller's
 // buffers -- window budget and number of passes of the windowed full-space
 // kernel with or without staged copies (or the single-pass kernel), lanes
-// per row, resident blocks per CU, LDS or global tables -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
+// per row, resident blocks per CU, LDS or global tables, cache hints on the
+// streaming accesses -- and pins the fastest for (Hamiltonian, nvec, dtype).  With
 // HPHI_TUNE_CACHE set, choices are appended to that file, keyed by a
 // signature of the device, the space and the packed operators, and are
 // reused by later processes without timing.
@@ -31,6 +32,7 @@ Schedule default_schedule(int nvec) {
     s.max_passes = 3;
     s.lpr = nvec >= 16 ? 4 : (nvec >= 8 ? 2 : 1);
     s.blocks_per_cu = 0;
+    s.nt_streams = nvec >= 8 ? 1 : 0;
     // overrides for experiments
     s.windowed = env_int("HPHI_WINDOWED", s.windowed);
     s.window_kb = env_int("HPHI_L2_WINDOW_KB", s.window_kb);
@@ -39,6 +41,7 @@ Schedule default_schedule(int nvec) {
     if (nvec >= 8 && (l == 1 || l == 2 || l == 4 || l == 8)) s.lpr = l;
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
     s.stage_tables = env_int("HPHI_STAGE_TABLES", s.stage_tables) ? 1 : 0;
+    s.nt_streams = env_int("HPHI_NT_STREAMS", s.nt_streams) ? 1 : 0;
     if (s.window_kb < 1) s.window_kb = 2048;
     if (s.max_passes < 1) s.max_passes = 1;
     return s;
@@ -72,8 +75,8 @@ bool cache_lookup(const std::string& sig, Schedule& out) {
     while (fgets(line, sizeof(line), f)) {
         char key[300];
         Schedule s;
-        if (sscanf(line, "%299s %d %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
-                   &s.blocks_per_cu, &s.stage_tables) == 7 &&
+        if (sscanf(line, "%299s %d %d %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
+                   &s.blocks_per_cu, &s.stage_tables, &s.nt_streams) == 8 &&
             sig == key) {
             out = s;   // the last entry for a key wins
             found = true;
@@ -88,8 +91,8 @@ void cache_store(const std::string& sig, const Schedule& s, double us) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
-            s.blocks_per_cu, s.stage_tables, us);
+    fprintf(f, "%s %d %d %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
+            s.blocks_per_cu, s.stage_tables, s.nt_streams, us);
     fclose(f);
 }
 
@@ -148,14 +151,17 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
             if (!windowable) continue;
             s.windowed = 1;
             cands.push_back(s);   // single natural pass, compact operators
-            for (int wkb : {1024, 2048, 4096})
-                for (int mp : {2, 3})
-                    for (int staged : {1, 2}) {
-                        s.windowed = staged;
-                        s.window_kb = wkb;
-                        s.max_passes = mp;
-                        cands.push_back(s);
-                    }
+            for (int nt : (nvec >= 8 ? std::vector<int>{1, 0} : std::vector<int>{0}))
+                for (int wkb : {1024, 2048, 4096})
+                    for (int mp : {2, 3})
+                        for (int staged : {1, 2}) {
+                            s.windowed = staged;
+                            s.window_kb = wkb;
+                            s.max_passes = mp;
+                            s.nt_streams = nt;
+                            cands.push_back(s);
+                        }
+            s.nt_streams = 0;
         }
     }
     hipEvent_t e0, e1;
@@ -214,7 +220,8 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
         sched_out[3] = best.lpr;
         sched_out[4] = best.blocks_per_cu;
         sched_out[5] = best.stage_tables;
-        sched_out[6] = int(best_us);
+        sched_out[6] = best.nt_streams;
+        sched_out[7] = int(best_us);
     }
     return HPHI_OK;
 }

@@ -619,3 +619,29 @@ def test_batched_lanczos_table_placement(monkeypatch, stage):
     for d, r in zip(descs, res):
         e0 = np.linalg.eigvalsh(oh.sparse_h(d, terms).toarray())[0]
         assert abs(r["e0_refined"] - e0) <= 1e-9 * max(1.0, abs(e0))
+
+
+@pytest.mark.parametrize("staged,passes", [(1, 2), (2, 3)])
+def test_streaming_hints_do_not_change_results(monkeypatch, staged, passes):
+    """Non-temporal hints on the windowed kernel's streaming accesses change cache policy only:
+    outputs and reductions are bitwise identical with and without them."""
+    desc = BasisDesc("spin", 12)
+    terms = kh_honeycomb_terms(lx=3, ly=2, random_dirs=True, seed=13)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(120, 136)), True)
+    vd = _to_dev(v, torch.complex64)
+    monkeypatch.setenv("HPHI_WINDOWED", str(staged))
+    monkeypatch.setenv("HPHI_L2_WINDOW_KB", "16")
+    monkeypatch.setenv("HPHI_PASSES", str(passes))
+    outs = []
+    for nt in (0, 1):
+        monkeypatch.setenv("HPHI_NT_STREAMS", str(nt))
+        red = torch.empty(64, dtype=torch.float64, device="cuda")
+        u = hp.hphi_hv(ham, vd, a=0.5, b=0.25, reduce=red)
+        outs.append((u.cpu().numpy(), red.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    ref = oh.sparse_h(desc, terms, st) @ vd.cpu().numpy().astype(np.complex128)
+    ref = 0.5 * ref + 0.25 * vd.cpu().numpy().astype(np.complex128)
+    assert np.linalg.norm(outs[1][0] - ref) <= 3e-6 * np.linalg.norm(ref)
