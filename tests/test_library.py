@@ -76,6 +76,11 @@ def test_entry_points_reject_null_handles(lib):
     assert lib.hphi_basis_dim(None, None) == L.HPHI_EINVAL
     lo = L.LanczosOptsC(10, 0, 0, 0, 0.0)
     assert lib.hphi_lanczos(None, 1, C.byref(lo), None, None, None, None, None) == L.HPHI_EINVAL
+    assert lib.hphi_expect(None, None, 1, 0, None, None) == L.HPHI_EINVAL
+    co = L.CgOptsC(1e-6, 2, 100, 1e-12)
+    cr = L.CgResultC()
+    assert lib.hphi_cg_refine(None, None, 0, -1.0, C.byref(co), None, C.byref(cr), None) == L.HPHI_EINVAL
+    assert lib.hphi_hv_tune(None, None, None, 16, 3, None, None) == L.HPHI_EINVAL
     lib.hphi_basis_free(None)
     lib.hphi_ham_free(None)
 
