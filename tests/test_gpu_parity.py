@@ -645,3 +645,41 @@ def test_streaming_hints_do_not_change_results(monkeypatch, staged, passes):
     ref = oh.sparse_h(desc, terms, st) @ vd.cpu().numpy().astype(np.complex128)
     ref = 0.5 * ref + 0.25 * vd.cpu().numpy().astype(np.complex128)
     assert np.linalg.norm(outs[1][0] - ref) <= 3e-6 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case", ["empty", "diagonal_only", "one_site", "two_site_full"])
+@pytest.mark.parametrize("nvec", [1, 16])
+def test_degenerate_hamiltonians_and_spaces(case, nvec):
+    """No terms (H = 0), a diagonal-only H (Ising + fields along z), a one-site space (two rows, below
+    one tile) and a two-site full space: outputs and reductions against the oracle."""
+    if case == "empty":
+        desc, terms = BasisDesc("spin", 8), []
+    elif case == "diagonal_only":
+        desc = BasisDesc("spin", 9, "sz", two_sz=1)
+        terms = [L.Term(L.SPIN_BOND, i, (i + 1) % 9, (0, 0, 0, 0, 0, 0, 0, 0, 0.7 + 0.1 * i)) for i in range(9)] + \
+            [L.Term(L.SPIN_FIELD, i, -1, (0.0, 0.0, 0.3 * i)) for i in range(9)]
+    elif case == "one_site":
+        desc, terms = BasisDesc("spin", 1), [L.Term(L.SPIN_FIELD, 0, -1, (0.5, 0.0, 0.25))]
+    else:
+        desc, terms = BasisDesc("spin", 2), [L.heisenberg_bond(0, 1, 1.3)]
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(140, 140 + nvec)), True)
+    vd = _to_dev(v, torch.complex128)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+    u = hp.hphi_hv(ham, vd, a=0.75, b=-0.5, reduce=red).cpu().numpy().reshape(len(st), nvec)
+    if terms:
+        H = oh.sparse_h(desc, terms, st)
+        hx = H @ v
+    else:
+        hx = np.zeros_like(v)
+    ref = 0.75 * hx - 0.5 * v
+    assert np.allclose(u, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
+    red = red.cpu().numpy().reshape(4, nvec)
+    for b in range(nvec):
+        want = [np.vdot(v[:, b], v[:, b]).real, np.vdot(v[:, b], hx[:, b]).real,
+                np.vdot(hx[:, b], hx[:, b]).real, np.vdot(ref[:, b], ref[:, b]).real]
+        assert np.allclose(red[:, b], want, rtol=1e-12, atol=1e-14)
