@@ -134,11 +134,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="kh_honeycomb24",
-                    choices=("kh_honeycomb24", "hubbard18", "heis_chain16", "hubbard_4x3", "tri24"),
+                    choices=("kh_honeycomb24", "kh_honeycomb24_cma", "hubbard18", "heis_chain16", "hubbard_4x3",
+                             "tri24"),
                     help="kh_honeycomb24: the headline (24-site Kitaev-Heisenberg TPQ, 16 complex64 samples); "
                          "hubbard18: the paper's 18-site Hubbard cluster at half filling (2,363,904,400 rows); "
                          "heis_chain16 / hubbard_4x3: FP64 Lanczos; tri24: the 13 Sz sectors of the 24-site "
-                         "triangular torus as one batched FP32 Lanczos")
+                         "triangular torus as one batched FP32 Lanczos; kh_honeycomb24_cma: the headline product "
+                         "through the dense-block (continuous-memory-access) variant")
+    ap.add_argument("--cluster-bits", type=int, default=6, help="kh_honeycomb24_cma: sites per dense cluster")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 5 for hubbard18)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3; 1 for hubbard18)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -184,6 +187,9 @@ def main():
         return
     if lanczos_mode:
         run_lanczos(args, hp, torch, np)
+        return
+    if args.workload == "kh_honeycomb24_cma":
+        run_cma(args, hp, torch, np)
         return
 
     w = workload("kh_honeycomb24")
@@ -458,6 +464,84 @@ def run_hubbard18(args, hp, torch, np):
                                          f"0..{rows_n - 1} of {dim}, one complex128 vector, {dt:.1f} s, "
                                          f"scaled by dim/rows"}
     print(json.dumps(res), flush=True)
+
+
+def run_cma(args, hp, torch, np):
+    """The headline product (24-site Kitaev-Heisenberg, 16 complex64 vectors, with the TPQ step's
+    a, b and reductions) through the dense-block variant, next to the pull product."""
+    from synth.configs import workload
+    from synth.vectors import device_uniform
+    w = workload("kh_honeycomb24")
+    nvec, ns, l, m = w.nvec, w.basis.n_sites, w.tpq_l, args.cluster_bits
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    dim = basis.dim
+    clusters = hp.hphi_hv_cma_plan(ham, m)
+    psi = device_uniform(dim, nvec, 915, True, torch.complex64)
+    u = torch.empty_like(psi)
+    red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+
+    def cma():
+        hp.hphi_hv_cma(ham, psi, u, cluster_bits=m, a=-1.0 / ns, b=l, reduce=red)
+
+    for _ in range(args.warmup):
+        cma()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cma()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms = _events_ms(cma, max(5, args.kernel_reps), torch)
+    red_cma = red.cpu().numpy().copy()
+    u_cma = u[:4096].cpu().numpy().copy()
+    # the pull product on the same input, tuned as in the headline run
+    sched = hp.hphi_hv_tune(ham, psi)
+
+    def pull():
+        hp.hphi_hv(ham, psi, u, a=-1.0 / ns, b=l, reduce=red)
+
+    pull()
+    torch.cuda.synchronize()
+    p_ms = _events_ms(pull, max(5, args.kernel_reps), torch)
+    red_pull = red.cpu().numpy()
+    u_pull = u[:4096].cpu().numpy()
+    V = dim * nvec * 8                                   # bytes of one 16-vector complex64 array
+    n_c = len(clusters)
+    # per cluster: read v, write u (and read u after the first); epilogue: read u and v, write u
+    alg_bytes = n_c * 2 * V + (n_c - 1) * V + 3 * V
+    flops = n_c * 2.0 * dim * (1 << m) * (2 * nvec)
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    out = {
+        "metric": "H·v products/s (dense-block variant)",
+        "value": args.steps / dt,
+        "unit": "H·v products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "kh_honeycomb24_cma_b16_c64", "n_sites": ns, "dim": dim, "nvec": nvec,
+                   "cluster_bits": m, "clusters": n_c, "storage": "complex64",
+                   "block_sums": "fp32 (MFMA)", "reductions": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one dense-block product call (all clusters and the epilogue)", "kernel_ms": k_ms,
+                     "algorithmic_bytes": alg_bytes},
+        "mfma": {"flop_per_product": flops, "achieved_tflops": flops / (k_ms * 1e-3) / 1e12,
+                 "peak_tflops": 157.3, "frac": flops / (k_ms * 1e-3) / 1e12 / 157.3},
+        "pull_product": {"ms": p_ms, "schedule": sched, "speedup_of_pull": k_ms / p_ms},
+        "agreement": {"max_rel_reduction_diff": float(np.max(np.abs(red_cma - red_pull) /
+                                                             np.maximum(np.abs(red_pull), 1e-300))),
+                      "max_abs_u_diff_first_4096_rows": float(np.abs(u_cma - u_pull).max())},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, w.terms, psi.cpu().numpy(), dim, nvec)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

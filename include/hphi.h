@@ -12,6 +12,8 @@
  *   - the Lanczos ground-state iteration with the second pass for the
  *     eigenvector and the energy/variance check (Sec. 3.4, App. A.3)
  *   - the microcanonical TPQ step                         (Sec. 3.5)
+ *   - a dense-block variant of the product after the continuous-memory-
+ *     access method, on the matrix cores                 (Sec. 4.3)
  *
  * Conventions (bind every entry point):
  *   * Site i of a spin-1/2 system is bit i (bit 0 least significant);
@@ -213,6 +215,39 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * space and operators.  Synchronizes `stream`. */
 int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
                  int32_t* sched_out, void* stream);
+
+/* Dense-block variant of the product, after the paper's continuous-memory-
+ * access method (Sec. 4.3): any sum of terms acting on M chosen sites is a
+ * dense 2^M x 2^M matrix acting on the 2^M rows that share all other bits.
+ * The terms are covered by clusters of at most `cluster_bits` = M sites
+ * (greedily, deterministic; every term must fit in one cluster); for each
+ * cluster the library builds its dense partial Hamiltonian once, and one
+ * pass multiplies every 2^M-row block by it with matrix-core (MFMA)
+ * instructions, gathering the block's rows through the cluster's bit
+ * positions instead of permuting the vector, and accumulating into u.  A
+ * final pass applies a, b, in_scale and the reductions exactly as hphi_hv
+ * does.  The result equals hphi_hv's up to rounding: the dense blocks sum in
+ * the storage precision (FP32 for F32/C64 storage, FP64 for F64/C128), and
+ * partial sums pass between clusters in u.
+ * Applies to spin-1/2 full spaces of 6..32 bits with real matrix elements;
+ * cluster_bits in 4..7 and at most the number of sites (6 for F64/C128).
+ * v, u: device, dim*nvec elements, interleaved; u must not alias v and must
+ * be non-NULL.  nvec in {1, 2, 4, 8, 16}.  opts as for hphi_hv (NULL =
+ * {1, 0, NULL, NULL}).  The dense matrices and the cluster plan are cached
+ * with the ham (2^(2M) values per cluster) until hphi_ham_free; calls that
+ * share a ham must not run concurrently on different streams.
+ * Returns HPHI_EINVAL if the space or the terms do not fit these limits,
+ * HPHI_EDTYPE for a complex Hamiltonian. */
+int hphi_hv_cma(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+                int32_t cluster_bits, const hphi_hv_opts* opts, void* stream);
+
+/* The cluster cover hphi_hv_cma uses for `cluster_bits` (building it if
+ * needed): *n_clusters receives the number of clusters (one pass each) and,
+ * if sites != NULL (host, n_clusters * cluster_bits entries, caller-owned),
+ * the sites of cluster c in ascending order at sites[c * cluster_bits ...].
+ * Call once with sites = NULL to learn the count.  Same limits and errors as
+ * hphi_hv_cma. */
+int hphi_hv_cma_plan(const hphi_ham* ham, int32_t cluster_bits, int32_t* n_clusters, int32_t* sites);
 
 /* Element export from the same device code that hphi_hv uses (parity checks).
  * For rows row0 .. row0+nrows-1, writes up to `cap` elements per row:

@@ -18,6 +18,8 @@ from .binding import (  # noqa: F401
     hphi_hv,
     hphi_hv_elements,
     hphi_hv_tune,
+    hphi_hv_cma,
+    hphi_hv_cma_plan,
     hphi_lanczos,
     hphi_tpq_step,
     version,

@@ -84,6 +84,9 @@ _SIGS = {
     "hphi_hv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(HvOptsC),
                  C.c_void_p], C.c_int),
     "hphi_hv_tune": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "hphi_hv_cma": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(HvOptsC),
+                     C.c_void_p], C.c_int),
+    "hphi_hv_cma_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
     "hphi_hv_elements": ([C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_lanczos": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(LanczosOptsC),

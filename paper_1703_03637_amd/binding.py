@@ -175,6 +175,31 @@ def hphi_hv(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None, *, a: f
     return u
 
 
+def hphi_hv_cma(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None, *, cluster_bits: int = 6,
+                a: float = 1.0, b: float = 0.0, in_scale: Optional[torch.Tensor] = None,
+                reduce: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Dense-block variant of hphi_hv (clusters of cluster_bits sites, MFMA blocks); same options."""
+    nv = _nvec(v, ham.dim)
+    if u is None:
+        u = torch.empty_like(v)
+    if u.shape != v.shape or u.dtype != v.dtype:
+        raise ValueError("u must match v in shape and dtype")
+    opts = L.HvOptsC(a, b, _ptr(in_scale), _ptr(reduce))
+    check(L.lib().hphi_hv_cma(C.c_void_p(ham.handle), _ptr(v), _ptr(u), nv, _dtype_code(v), int(cluster_bits),
+                              C.byref(opts), _stream()))
+    return u
+
+
+def hphi_hv_cma_plan(ham: Ham, cluster_bits: int = 6) -> list:
+    """The clusters (lists of sites) hphi_hv_cma uses for cluster_bits."""
+    n = C.c_int32(0)
+    check(L.lib().hphi_hv_cma_plan(C.c_void_p(ham.handle), int(cluster_bits), C.byref(n), None))
+    sites = (C.c_int32 * (n.value * int(cluster_bits)))()
+    check(L.lib().hphi_hv_cma_plan(C.c_void_p(ham.handle), int(cluster_bits), C.byref(n), sites))
+    m = int(cluster_bits)
+    return [list(sites[c * m:(c + 1) * m]) for c in range(n.value)]
+
+
 def hphi_hv_tune(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None) -> dict:
     """Autotune the product schedule for v's nvec and dtype; returns the chosen schedule."""
     nv = _nvec(v, ham.dim)

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhphi.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "basis.cpp", "ham.cpp", "plan.cpp", "tune.cpp", "tridiag.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "basis.cpp", "ham.cpp", "plan.cpp", "cma.cpp", "tune.cpp", "tridiag.cpp"]
 ARCH = os.environ.get("HPHI_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

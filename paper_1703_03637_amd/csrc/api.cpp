@@ -62,6 +62,47 @@ extern "C" int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec
     return launch_hv(L, (hipStream_t)stream);
 }
 
+extern "C" int hphi_hv_cma(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t dtype,
+                           int32_t cluster_bits, const hphi_hv_opts* opts, void* stream) {
+    if (!ham || !v || !u) return set_error(HPHI_EINVAL, "hphi_hv_cma: null ham, v or u");
+    if (u == v) return set_error(HPHI_EINVAL, "hphi_hv_cma: u must not alias v");
+    if (!valid_nvec(nvec)) return set_error(HPHI_EINVAL, "hphi_hv_cma: nvec must be 1, 2, 4, 8 or 16");
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_hv_cma: bad dtype %d", dtype);
+    if (ham->is_complex) return set_error(HPHI_EDTYPE, "hphi_hv_cma: complex matrix elements");
+    hphi_hv_opts o = opts ? *opts : hphi_hv_opts{1.0, 0.0, nullptr, nullptr};
+    if (!std::isfinite(o.a) || !std::isfinite(o.b)) return set_error(HPHI_EINVAL, "hphi_hv_cma: non-finite a or b");
+    if ((dtype == HPHI_F64 || dtype == HPHI_C128) && cluster_bits > 6)
+        return set_error(HPHI_EINVAL, "hphi_hv_cma: FP64 storage allows cluster_bits <= 6");
+    const CmaPlan* P = nullptr;
+    const int rc = get_cma_plan(ham, cluster_bits, &P);
+    if (rc) return rc;
+    HvLaunch L{};
+    L.ham = ham;
+    L.v = v;
+    L.u = u;
+    L.sx = o.in_scale;
+    L.a = o.a;
+    L.b = o.b;
+    L.nvec = int(nvec);
+    L.dtype = dtype;
+    L.reduce_out = o.reduce;
+    return launch_hv_cma(L, P, (hipStream_t)stream);
+}
+
+extern "C" int hphi_hv_cma_plan(const hphi_ham* ham, int32_t cluster_bits, int32_t* n_clusters, int32_t* sites) {
+    if (!ham || !n_clusters) return set_error(HPHI_EINVAL, "hphi_hv_cma_plan: null ham or n_clusters");
+    const CmaPlan* P = nullptr;
+    const int rc = get_cma_plan(ham, cluster_bits, &P);
+    if (rc) return rc;
+    *n_clusters = P->n_stage;
+    if (sites) {
+        // cluster bits in ascending order (the plan lists them so)
+        for (int c = 0; c < P->n_stage; ++c)
+            for (int j = 0; j < P->M; ++j) sites[c * P->M + j] = P->bits[size_t(c) * 64 + j];
+    }
+    return HPHI_OK;
+}
+
 extern "C" int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap, int64_t* cols,
                                 double* re, double* im, int32_t* term_id, int32_t* counts, void* stream) {
     if (!ham) return set_error(HPHI_EINVAL, "hphi_hv_elements: null ham");

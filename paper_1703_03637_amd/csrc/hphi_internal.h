@@ -97,6 +97,22 @@ struct PassPlan {
     int32_t* d_inv = nullptr;
 };
 
+// Dense-block plan (clusters of M configuration bits).  Stage c applies the
+// dense partial Hamiltonian of cluster c, H_c[r][t] (row r pulls from
+// column t, both M-bit local configurations), to every block of 2^M rows
+// that share all configuration bits outside the cluster.
+struct CmaPlan {
+    int M = 0;
+    int n_stage = 0;
+    // [n_stage][64]: local bit j < M -> configuration bit of the cluster,
+    // then the configuration bits outside it, ascending (block index bits)
+    std::vector<int32_t> bits;
+    std::vector<int32_t> n_ops;     // [n_stage] operators folded into each cluster
+    float* d_hf = nullptr;          // [n_stage][2^M][2^M], row-major
+    double* d_hd = nullptr;         // same, FP64
+    int32_t* d_bits = nullptr;      // device copy of bits
+};
+
 // Device view of a basis, passed by value to kernels.
 struct BasisDev {
     int32_t sector;       // 0 = full space (index = bit string)
@@ -148,6 +164,7 @@ struct hphi_ham {
     void* d_stage[2] = {nullptr, nullptr};   // copies of v in a later pass's order (staged schedule)
     size_t stage_bytes[2] = {0, 0};
     std::vector<hphi::PassPlan*> plans;
+    std::vector<hphi::CmaPlan*> cma_plans;
     struct Tuned {
         int nvec, dtype;
         hphi::Schedule s;
@@ -269,6 +286,12 @@ int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta,
 int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec,
                        hipStream_t st);
 int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st);
+
+// dense-block plan for clusters of M bits (cma.cpp); an error code if the
+// space or the operators do not fit
+int get_cma_plan(const hphi_ham* ham, int M, const CmaPlan** out);
+// one dense-block product (kernels.hip): stages into u, then the epilogue
+int launch_hv_cma(const HvLaunch& L, const CmaPlan* P, hipStream_t st);
 
 // pass plan of the windowed product (plan.cpp); nullptr if not applicable
 const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes);

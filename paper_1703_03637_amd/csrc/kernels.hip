@@ -24,6 +24,8 @@
 #include <cstdlib>
 #include <vector>
 
+#include <type_traits>
+
 #include "hphi_internal.h"
 
 namespace hphi {
@@ -898,6 +900,173 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     }
 }
 
+// ---- dense-block (CMA) product.  Stage c: for every block of D = 2^M rows
+// that share the configuration bits outside cluster c, U_blk += H_c V_blk,
+// where V_blk is D rows x RC real columns (the interleaved vectors, complex
+// parts as separate columns; H_c is real).  A workgroup stages H_c in LDS
+// once, then per block gathers the D rows through the cluster's bit
+// positions into LDS and multiplies with 16x16x4 MFMA tiles (FP32 for FP32
+// storage, FP64 for FP64 storage): wave w takes the 16-row tiles w, w+4, ...
+// and every 16-column tile.  The stage result is added to u (written on the
+// first stage), in the storage type.
+struct CmaArgs {
+    const void* v;
+    void* u;
+    const void* h;         // [D][D] dense partial Hamiltonian of this stage (S)
+    const int32_t* bits;   // [64]: local bit -> configuration bit, then the block-index bits
+    int nbits;
+    int first;
+    int64_t n_blocks;
+};
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <typename S>
+struct MfmaAcc;
+// Operand layouts (both): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result register r of lane l is D[row(l, r)][l % 16]; the row mapping
+// differs between the FP32 and FP64 instructions (checked on gfx950).
+template <>
+struct MfmaAcc<float> {
+    using type = f32x4_t;
+    static __device__ __forceinline__ type step(float a, float b, type c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+    using type = f64x4_t;
+    static __device__ __forceinline__ type step(double a, double b, type c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename S, int RC, int M>
+struct CmaShape {
+    static constexpr int D = 1 << M;
+    static constexpr int NT = (RC + 15) / 16;       // 16-column tiles
+    static constexpr int HLD = D + 1;               // LDS row stride of H_c (bank spread)
+    static constexpr int VLD = NT * 16 + 1;         // LDS row stride of V_blk
+    static constexpr size_t lds_bytes = (size_t(D) * HLD + size_t(D) * VLD) * sizeof(S) + size_t(D) * 4;
+};
+
+template <typename S, int RC, int M>
+__global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
+    using Sh = CmaShape<S, RC, M>;
+    constexpr int D = Sh::D, NT = Sh::NT, HLD = Sh::HLD, VLD = Sh::VLD;
+    constexpr int RPI = kBlock / RC >= 1 ? kBlock / RC : 1;   // rows per gather step (RC divides kBlock)
+    static_assert(kBlock % RC == 0, "row width must divide the block");
+    S* hs = reinterpret_cast<S*>(lds_dyn);
+    S* vs = hs + size_t(D) * HLD;
+    uint32_t* lcfg = reinterpret_cast<uint32_t*>(vs + size_t(D) * VLD);
+    const S* __restrict__ v = static_cast<const S*>(A.v);
+    S* __restrict__ u = static_cast<S*>(A.u);
+    const S* __restrict__ h = static_cast<const S*>(A.h);
+    typedef const __attribute__((address_space(4))) int32_t ConstI32;
+    const ConstI32* bits = (const ConstI32*)(A.bits);
+    const int tid = int(threadIdx.x);
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+
+    // H_c and the configuration bits of each local row, once per workgroup
+    for (int i = tid; i < D * D; i += kBlock) hs[(i / D) * HLD + (i % D)] = h[i];
+    for (int r = tid; r < D; r += kBlock) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if ((r >> j) & 1) c |= 1u << bits[j];
+        lcfg[r] = c;
+    }
+    // zero the padding columns of V_blk once (tiles read them; they never change)
+    if constexpr (NT * 16 > RC) {
+        constexpr int PADC = NT * 16 - RC;
+        for (int i = tid; i < D * PADC; i += kBlock) vs[(i / PADC) * VLD + RC + i % PADC] = S(0);
+    }
+    __syncthreads();
+
+    const int xcd = blockIdx.x & 7;
+    const int64_t per_x = (A.n_blocks + 7) >> 3;
+    const int64_t b_begin = xcd * per_x;
+    const int64_t b_end = (b_begin + per_x < A.n_blocks) ? b_begin + per_x : A.n_blocks;
+    const int g_row = tid / RC, g_col = tid % RC;
+
+    for (int64_t blk = b_begin + (blockIdx.x >> 3); blk < b_end; blk += (gridDim.x >> 3)) {
+        uint32_t s_blk = 0;
+        for (int j = 0; j < A.nbits - M; ++j)
+            if ((blk >> j) & 1) s_blk |= 1u << bits[M + j];
+        // gather the block's rows
+        for (int r0 = 0; r0 < D; r0 += RPI) {
+            const int r = r0 + g_row;
+            if (r < D) vs[r * VLD + g_col] = v[size_t(s_blk | lcfg[r]) * RC + g_col];
+        }
+        __syncthreads();
+        for (int rt = wave; rt < D / 16; rt += kWavesPerBlock) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                typename MfmaAcc<S>::type acc = {S(0), S(0), S(0), S(0)};
+                const S* ha = hs + (rt * 16 + (lane & 15)) * HLD + (lane >> 4);
+                const S* vb = vs + (lane >> 4) * VLD + nt * 16 + (lane & 15);
+#pragma unroll 4
+                for (int k0 = 0; k0 < D; k0 += 4) acc = MfmaAcc<S>::step(ha[k0], vb[k0 * VLD], acc);
+                const int col = nt * 16 + (lane & 15);
+                if (col < RC) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = rt * 16 + MfmaAcc<S>::row(lane, i);
+                        S* dst = u + size_t(s_blk | lcfg[r]) * RC + col;
+                        *dst = A.first ? acc[i] : S(*dst + acc[i]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the next gather overwrites V_blk
+    }
+}
+
+// Final pass of the dense-block product: u holds H v (unscaled); apply the
+// input scale, a and b, and the four FP64 reductions per vector.  Thread t
+// always handles vector t % B (the grid stride is a multiple of B).
+template <typename S, bool CPLX, int B>
+__global__ __launch_bounds__(256) void cma_epilogue_kernel(const S* __restrict__ v, S* __restrict__ u, int64_t n,
+                                                           double a, double b, const double* __restrict__ sx,
+                                                           double* __restrict__ partials) {
+    constexpr int NC = CPLX ? 2 : 1;
+    const int vec = int(threadIdx.x) % B;
+    const double sc = sx ? sx[vec] : 1.0;
+    double q[kNQ] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+        double hv[NC], xv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            hv[c] = sc * double(u[e * NC + c]);
+            xv[c] = sc * double(v[e * NC + c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double o = a * hv[c] + b * xv[c];
+            u[e * NC + c] = S(o);
+            q[0] += xv[c] * xv[c];
+            q[1] += xv[c] * hv[c];
+            q[2] += hv[c] * hv[c];
+            q[3] += o * o;
+        }
+    }
+    if (!partials) return;
+    __shared__ double sh[kNQ][256];
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) sh[k][threadIdx.x] = q[k];
+    __syncthreads();
+    if (int(threadIdx.x) < kNQ * B) {
+        const int k = threadIdx.x / B, bv = threadIdx.x % B;
+        double acc = 0.0;
+        for (int t = bv; t < 256; t += B) acc += sh[k][t];
+        partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = acc;
+    }
+}
+
 // out[q] = sum over g of partials[g * nq + q], fixed order
 __device__ __forceinline__ void reduce_body(const double* __restrict__ partials, int n_parts, int nq, int q,
                                             double* __restrict__ out) {
@@ -1432,6 +1601,94 @@ static int launch_hv_s(const HvLaunch& L, hipStream_t st) {
     if (w != 1) return w;
     if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true>(L, sc, st);
     return launch_hv_b<S, CPLX, CCOEF, false>(L, sc, st);
+}
+
+// ---- dense-block product launch
+template <typename S, int RC, int M>
+static int launch_cma_stages(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
+    using Sh = CmaShape<S, RC, M>;
+    const hphi_ham* H = L.ham;
+    const size_t lds = Sh::lds_bytes;
+    int dev = 0, max_lds = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        max_lds = 64 * 1024;
+    if (lds > size_t(max_lds))
+        return set_error(HPHI_EINVAL, "dense-block product: %d-bit clusters need %zu bytes of LDS", M, lds);
+    static const int occ = occupancy_blocks(cma_kernel<S, RC, M>);
+    const int per_cu = occupancy_with_lds(occ, lds);
+    CmaArgs A;
+    A.v = L.v;
+    A.u = L.u;
+    A.nbits = H->basis->nbits;
+    A.n_blocks = int64_t(1) << (A.nbits - M);
+    int64_t g = int64_t(per_cu) * cu_count();
+    if (g > A.n_blocks) g = A.n_blocks;
+    g = ((g + 7) / 8) * 8;
+    const size_t D2 = size_t(1) << (2 * M);
+    for (int c = 0; c < P->n_stage; ++c) {
+        A.h = std::is_same<S, float>::value ? static_cast<const void*>(P->d_hf + c * D2)
+                                            : static_cast<const void*>(P->d_hd + c * D2);
+        A.bits = P->d_bits + size_t(c) * 64;
+        A.first = c == 0 ? 1 : 0;
+        cma_kernel<S, RC, M><<<int(g), kBlock, lds, st>>>(A);
+        const int rc = check_hip(hipGetLastError(), "cma_kernel launch");
+        if (rc) return rc;
+    }
+    return HPHI_OK;
+}
+
+template <typename S, int RC>
+static int launch_cma_m(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
+    switch (P->M) {
+        case 4: return launch_cma_stages<S, RC, 4>(L, P, st);
+        case 5: return launch_cma_stages<S, RC, 5>(L, P, st);
+        case 6: return launch_cma_stages<S, RC, 6>(L, P, st);
+        case 7:
+            if constexpr (sizeof(S) == 4) return launch_cma_stages<S, RC, 7>(L, P, st);
+            break;
+    }
+    return set_error(HPHI_EINVAL, "dense-block product: cluster_bits %d not supported for this dtype", P->M);
+}
+
+template <typename S, bool CPLX, int B>
+static int launch_cma_b(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
+    constexpr int RC = B * (CPLX ? 2 : 1);
+    int rc = launch_cma_m<S, RC>(L, P, st);
+    if (rc) return rc;
+    const int64_t n = L.ham->basis->dim * B;
+    int64_t g = (n + 255) / 256;
+    if (g > 2048) g = 2048;
+    g = (g / 8 > 0 ? g / 8 * 8 : 8);
+    double* partials = L.reduce_out ? L.ham->d_partials : nullptr;
+    cma_epilogue_kernel<S, CPLX, B><<<int(g), 256, 0, st>>>(static_cast<const S*>(L.v), static_cast<S*>(L.u), n,
+                                                           L.a, L.b, L.sx, partials);
+    rc = check_hip(hipGetLastError(), "cma_epilogue launch");
+    if (rc || !L.reduce_out) return rc;
+    reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(L.ham->d_partials, int(g), kNQ * B, L.reduce_out, nullptr);
+    return check_hip(hipGetLastError(), "reduce launch");
+}
+
+template <typename S, bool CPLX>
+static int launch_cma_s(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
+    switch (L.nvec) {
+        case 1: return launch_cma_b<S, CPLX, 1>(L, P, st);
+        case 2: return launch_cma_b<S, CPLX, 2>(L, P, st);
+        case 4: return launch_cma_b<S, CPLX, 4>(L, P, st);
+        case 8: return launch_cma_b<S, CPLX, 8>(L, P, st);
+        case 16: return launch_cma_b<S, CPLX, 16>(L, P, st);
+    }
+    return set_error(HPHI_EINVAL, "nvec must be 1, 2, 4, 8 or 16 (got %d)", L.nvec);
+}
+
+int launch_hv_cma(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
+    switch (L.dtype) {
+        case HPHI_F64: return launch_cma_s<double, false>(L, P, st);
+        case HPHI_F32: return launch_cma_s<float, false>(L, P, st);
+        case HPHI_C128: return launch_cma_s<double, true>(L, P, st);
+        case HPHI_C64: return launch_cma_s<float, true>(L, P, st);
+    }
+    return set_error(HPHI_EINVAL, "bad dtype %d", L.dtype);
 }
 
 int launch_hv(const HvLaunch& L, hipStream_t st) {

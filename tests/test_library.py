@@ -81,6 +81,8 @@ def test_entry_points_reject_null_handles(lib):
     cr = L.CgResultC()
     assert lib.hphi_cg_refine(None, None, 0, -1.0, C.byref(co), None, C.byref(cr), None) == L.HPHI_EINVAL
     assert lib.hphi_hv_tune(None, None, None, 16, 3, None, None) == L.HPHI_EINVAL
+    assert lib.hphi_hv_cma(None, None, None, 16, 3, 6, C.byref(opts), None) == L.HPHI_EINVAL
+    assert lib.hphi_hv_cma_plan(None, 6, None, None) == L.HPHI_EINVAL
     lib.hphi_basis_free(None)
     lib.hphi_ham_free(None)
 
