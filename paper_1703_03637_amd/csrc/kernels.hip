@@ -947,21 +947,51 @@ struct MfmaAcc<double> {
 template <typename S, int RC, int M>
 struct CmaShape {
     static constexpr int D = 1 << M;
-    static constexpr int NT = (RC + 15) / 16;       // 16-column tiles
-    static constexpr int HLD = D + 1;               // LDS row stride of H_c (bank spread)
-    static constexpr int VLD = NT * 16 + 1;         // LDS row stride of V_blk
-    static constexpr size_t lds_bytes = (size_t(D) * HLD + size_t(D) * VLD) * sizeof(S) + size_t(D) * 4;
+    static constexpr int NT = (RC + 15) / 16;                   // 16-column tiles
+    static constexpr int RB = RC * int(sizeof(S));               // bytes of one row of the block
+    static constexpr int CB = RB >= 16 ? 16 : RB;                // copy chunk
+    static constexpr int CPR = RB / CB;                          // chunks per row
+    static constexpr int EPC = CB / int(sizeof(S));              // scalars per chunk
+    // V_blk row stride (scalars): 16-byte aligned, and for FP32 the four
+    // 16-lane groups of an operand read land on different bank halves
+    static constexpr int VLD = sizeof(S) == 4 ? (NT * 16 + ((NT & 1) ? 0 : 16)) : NT * 16 + 2;
+    // output tile row stride: 16-byte aligned, rows 4 apart on other banks
+    static constexpr int OLD = sizeof(S) == 4 ? ((RC + 3) / 4 * 4 + 4) : (RC + 1) / 2 * 2 + 2;
+    static constexpr int TPW = (D / 16 + kWavesPerBlock - 1) / kWavesPerBlock;   // row tiles per wave
+    static constexpr size_t lds_bytes = (size_t(D) * VLD + size_t(D) * OLD) * sizeof(S) + size_t(D) * 4;
 };
 
+template <int CB>
+struct ChunkT;
+template <>
+struct ChunkT<16> {
+    using type = uint4;
+};
+template <>
+struct ChunkT<8> {
+    using type = uint2;
+};
+template <>
+struct ChunkT<4> {
+    using type = uint32_t;
+};
+
+// Stage kernel.  Per block: the rows were gathered into V_blk (LDS) by the
+// previous iteration; each wave multiplies its 16-row tiles of H_c (held in
+// registers for the whole launch) by V_blk, writes the tile to the output
+// tile in LDS; after a barrier the block adds the output tile to u row by
+// row (16-byte accesses) while gathering the next block's rows.
 template <typename S, int RC, int M>
 __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     using Sh = CmaShape<S, RC, M>;
-    constexpr int D = Sh::D, NT = Sh::NT, HLD = Sh::HLD, VLD = Sh::VLD;
-    constexpr int RPI = kBlock / RC >= 1 ? kBlock / RC : 1;   // rows per gather step (RC divides kBlock)
-    static_assert(kBlock % RC == 0, "row width must divide the block");
-    S* hs = reinterpret_cast<S*>(lds_dyn);
-    S* vs = hs + size_t(D) * HLD;
-    uint32_t* lcfg = reinterpret_cast<uint32_t*>(vs + size_t(D) * VLD);
+    constexpr int D = Sh::D, NT = Sh::NT, VLD = Sh::VLD, OLD = Sh::OLD, TPW = Sh::TPW;
+    constexpr int CB = Sh::CB, CPR = Sh::CPR, EPC = Sh::EPC;
+    using Chunk = typename ChunkT<CB>::type;
+    static_assert(kBlock % CPR == 0, "chunks of a row divide the block");
+    constexpr int RPI = kBlock / CPR;                            // rows per copy step
+    S* vs = reinterpret_cast<S*>(lds_dyn);
+    S* os = vs + size_t(D) * VLD;
+    uint32_t* lcfg = reinterpret_cast<uint32_t*>(os + size_t(D) * OLD);
     const S* __restrict__ v = static_cast<const S*>(A.v);
     S* __restrict__ u = static_cast<S*>(A.u);
     const S* __restrict__ h = static_cast<const S*>(A.h);
@@ -971,8 +1001,16 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     const int lane = tid & 63;
     const int wave = wave_uniform(tid >> 6);
 
-    // H_c and the configuration bits of each local row, once per workgroup
-    for (int i = tid; i < D * D; i += kBlock) hs[(i / D) * HLD + (i % D)] = h[i];
+    // the wave's A operands for the whole launch: lane holds
+    // H_c[rt*16 + lane % 16][4k + lane / 16], k = 0 .. D/4 - 1
+    S ha[TPW][D / 4];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int rt = wave + t * kWavesPerBlock;
+#pragma unroll
+        for (int k = 0; k < D / 4; ++k)
+            ha[t][k] = rt < D / 16 ? h[size_t(rt * 16 + (lane & 15)) * D + 4 * k + (lane >> 4)] : S(0);
+    }
     for (int r = tid; r < D; r += kBlock) {
         uint32_t c = 0;
 #pragma unroll
@@ -980,49 +1018,94 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
             if ((r >> j) & 1) c |= 1u << bits[j];
         lcfg[r] = c;
     }
-    // zero the padding columns of V_blk once (tiles read them; they never change)
+    // padding columns of V_blk are read by the last column tile and never change
     if constexpr (NT * 16 > RC) {
         constexpr int PADC = NT * 16 - RC;
         for (int i = tid; i < D * PADC; i += kBlock) vs[(i / PADC) * VLD + RC + i % PADC] = S(0);
     }
-    __syncthreads();
 
     const int xcd = blockIdx.x & 7;
     const int64_t per_x = (A.n_blocks + 7) >> 3;
     const int64_t b_begin = xcd * per_x;
     const int64_t b_end = (b_begin + per_x < A.n_blocks) ? b_begin + per_x : A.n_blocks;
-    const int g_row = tid / RC, g_col = tid % RC;
-
-    for (int64_t blk = b_begin + (blockIdx.x >> 3); blk < b_end; blk += (gridDim.x >> 3)) {
-        uint32_t s_blk = 0;
+    const int64_t b_step = gridDim.x >> 3;
+    const int c_row = tid / CPR, c_chunk = tid % CPR;
+    auto block_bits = [&](int64_t blk) {
+        uint32_t sb = 0;
         for (int j = 0; j < A.nbits - M; ++j)
-            if ((blk >> j) & 1) s_blk |= 1u << bits[M + j];
-        // gather the block's rows
+            if ((blk >> j) & 1) sb |= 1u << bits[M + j];
+        return sb;
+    };
+    auto gather = [&](uint32_t sb) {
+#pragma unroll 4
         for (int r0 = 0; r0 < D; r0 += RPI) {
-            const int r = r0 + g_row;
-            if (r < D) vs[r * VLD + g_col] = v[size_t(s_blk | lcfg[r]) * RC + g_col];
+            const int r = r0 + c_row;
+            if (RPI <= D || r < D) {
+                const Chunk w = *reinterpret_cast<const Chunk*>(v + size_t(sb | lcfg[r]) * RC + c_chunk * EPC);
+                *reinterpret_cast<Chunk*>(vs + r * VLD + c_chunk * EPC) = w;
+            }
         }
-        __syncthreads();
-        for (int rt = wave; rt < D / 16; rt += kWavesPerBlock) {
+    };
+
+    __syncthreads();   // lcfg ready
+    int64_t blk = b_begin + (blockIdx.x >> 3);
+    uint32_t sb = blk < b_end ? block_bits(blk) : 0u;
+    if (blk < b_end) gather(sb);
+    __syncthreads();
+    for (; blk < b_end; blk += b_step) {
+        // multiply: independent accumulators per row tile and column tile
+        typename MfmaAcc<S>::type acc[TPW][NT];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[t][nt] = {S(0), S(0), S(0), S(0)};
+        const S* vb = vs + (lane >> 4) * VLD + (lane & 15);
+#pragma unroll
+        for (int k = 0; k < D / 4; ++k) {
+            S b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b[nt] = vb[4 * k * VLD + nt * 16];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[t][nt] = MfmaAcc<S>::step(ha[t][k], b[nt], acc[t][nt]);
+        }
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int rt = wave + t * kWavesPerBlock;
+            if (rt >= D / 16) continue;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                typename MfmaAcc<S>::type acc = {S(0), S(0), S(0), S(0)};
-                const S* ha = hs + (rt * 16 + (lane & 15)) * HLD + (lane >> 4);
-                const S* vb = vs + (lane >> 4) * VLD + nt * 16 + (lane & 15);
-#pragma unroll 4
-                for (int k0 = 0; k0 < D; k0 += 4) acc = MfmaAcc<S>::step(ha[k0], vb[k0 * VLD], acc);
                 const int col = nt * 16 + (lane & 15);
                 if (col < RC) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = rt * 16 + MfmaAcc<S>::row(lane, i);
-                        S* dst = u + size_t(s_blk | lcfg[r]) * RC + col;
-                        *dst = A.first ? acc[i] : S(*dst + acc[i]);
-                    }
+                    for (int i = 0; i < 4; ++i) os[(rt * 16 + MfmaAcc<S>::row(lane, i)) * OLD + col] = acc[t][nt][i];
                 }
             }
         }
-        __syncthreads();   // the next gather overwrites V_blk
+        __syncthreads();   // output tile complete; V_blk free
+        // add the output tile to u, and gather the next block
+        const uint32_t sb_cur = sb;
+        const int64_t nxt = blk + b_step;
+        if (nxt < b_end) sb = block_bits(nxt);
+#pragma unroll 2
+        for (int r0 = 0; r0 < D; r0 += RPI) {
+            const int r = r0 + c_row;
+            if (RPI <= D || r < D) {
+                S* dst = u + size_t(sb_cur | lcfg[r]) * RC + c_chunk * EPC;
+                alignas(16) S o[EPC];
+                *reinterpret_cast<Chunk*>(o) = *reinterpret_cast<const Chunk*>(os + r * OLD + c_chunk * EPC);
+                if (!A.first) {
+                    alignas(16) S p[EPC];
+                    *reinterpret_cast<Chunk*>(p) = *reinterpret_cast<const Chunk*>(dst);
+#pragma unroll
+                    for (int e = 0; e < EPC; ++e) o[e] = S(o[e] + p[e]);
+                }
+                *reinterpret_cast<Chunk*>(dst) = *reinterpret_cast<const Chunk*>(o);
+            }
+        }
+        if (nxt < b_end) gather(sb);
+        __syncthreads();   // next V_blk in place; output tile free
     }
 }
 
