@@ -224,9 +224,9 @@ int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int3
  * cluster the library builds its dense partial Hamiltonian once, and one
  * pass multiplies every 2^M-row block by it with matrix-core (MFMA)
  * instructions, gathering the block's rows through the cluster's bit
- * positions instead of permuting the vector, and accumulating into u.  A
- * final pass applies a, b, in_scale and the reductions exactly as hphi_hv
- * does.  The result equals hphi_hv's up to rounding: the dense blocks sum in
+ * positions instead of permuting the vector, and accumulating into u.  The
+ * last cluster's pass also applies a, b, in_scale and the reductions exactly
+ * as hphi_hv does.  The result equals hphi_hv's up to rounding: the dense blocks sum in
  * the storage precision (FP32 for F32/C64 storage, FP64 for F64/C128), and
  * partial sums pass between clusters in u.
  * Applies to spin-1/2 full spaces of 6..32 bits with real matrix elements;

@@ -915,8 +915,12 @@ struct CmaArgs {
     const void* h;         // [D][D] dense partial Hamiltonian of this stage (S)
     const int32_t* bits;   // [64]: local bit -> configuration bit, then the block-index bits
     int nbits;
-    int first;
+    int first;             // stage 0: write u instead of adding to it
+    int last;              // last stage: apply a, b, the input scale and the reductions
     int64_t n_blocks;
+    double a, b;
+    const double* sx;      // [nvec] input scale or nullptr
+    double* partials;      // last stage: [grid][kNQ * nvec] block sums, or nullptr
 };
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -980,8 +984,12 @@ struct ChunkT<4> {
 // previous iteration; each wave multiplies its 16-row tiles of H_c (held in
 // registers for the whole launch) by V_blk, writes the tile to the output
 // tile in LDS; after a barrier the block adds the output tile to u row by
-// row (16-byte accesses) while gathering the next block's rows.
-template <typename S, int RC, int M>
+// row (16-byte accesses) while gathering the next block's rows.  The last
+// stage also finishes the product there: with x = s v (the row's own values
+// are in V_blk) and h the accumulated H v, it stores a h + b x and sums the
+// four FP64 quantities per vector (a thread's chunk always holds the same
+// vectors; wave shuffles, then a fixed-order block sum).
+template <typename S, bool CPLX, int RC, int M>
 __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     using Sh = CmaShape<S, RC, M>;
     constexpr int D = Sh::D, NT = Sh::NT, VLD = Sh::VLD, OLD = Sh::OLD, TPW = Sh::TPW;
@@ -989,6 +997,10 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     using Chunk = typename ChunkT<CB>::type;
     static_assert(kBlock % CPR == 0, "chunks of a row divide the block");
     constexpr int RPI = kBlock / CPR;                            // rows per copy step
+    constexpr int NC = CPLX ? 2 : 1;
+    constexpr int B = RC / NC;                                   // vectors
+    constexpr int VPT = EPC / NC;                                // vectors in a thread's chunk
+    static_assert(VPT >= 1 && EPC % NC == 0, "a chunk holds whole elements");
     S* vs = reinterpret_cast<S*>(lds_dyn);
     S* os = vs + size_t(D) * VLD;
     uint32_t* lcfg = reinterpret_cast<uint32_t*>(os + size_t(D) * OLD);
@@ -1030,6 +1042,14 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     const int64_t b_end = (b_begin + per_x < A.n_blocks) ? b_begin + per_x : A.n_blocks;
     const int64_t b_step = gridDim.x >> 3;
     const int c_row = tid / CPR, c_chunk = tid % CPR;
+    double scl[VPT];
+    double q[kNQ][VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        scl[j] = (A.last && A.sx) ? A.sx[c_chunk * VPT + j] : 1.0;
+#pragma unroll
+        for (int k = 0; k < kNQ; ++k) q[k][j] = 0.0;
+    }
     auto block_bits = [&](int64_t blk) {
         uint32_t sb = 0;
         for (int j = 0; j < A.nbits - M; ++j)
@@ -1101,52 +1121,52 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
 #pragma unroll
                     for (int e = 0; e < EPC; ++e) o[e] = S(o[e] + p[e]);
                 }
+                if (A.last) {
+                    // the row's own values: this thread's chunk of V_blk (only this
+                    // thread rewrites it, in the gather below)
+                    alignas(16) S x[EPC];
+                    *reinterpret_cast<Chunk*>(x) = *reinterpret_cast<const Chunk*>(vs + r * VLD + c_chunk * EPC);
+#pragma unroll
+                    for (int j = 0; j < VPT; ++j) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            const int e = j * NC + c;
+                            const double hv = scl[j] * double(o[e]);
+                            const double xv = scl[j] * double(x[e]);
+                            const double ov = A.a * hv + A.b * xv;
+                            o[e] = S(ov);
+                            q[0][j] += xv * xv;
+                            q[1][j] += xv * hv;
+                            q[2][j] += hv * hv;
+                            q[3][j] += ov * ov;
+                        }
+                    }
+                }
                 *reinterpret_cast<Chunk*>(dst) = *reinterpret_cast<const Chunk*>(o);
             }
         }
         if (nxt < b_end) gather(sb);
         __syncthreads();   // next V_blk in place; output tile free
     }
-}
-
-// Final pass of the dense-block product: u holds H v (unscaled); apply the
-// input scale, a and b, and the four FP64 reductions per vector.  Thread t
-// always handles vector t % B (the grid stride is a multiple of B).
-template <typename S, bool CPLX, int B>
-__global__ __launch_bounds__(256) void cma_epilogue_kernel(const S* __restrict__ v, S* __restrict__ u, int64_t n,
-                                                           double a, double b, const double* __restrict__ sx,
-                                                           double* __restrict__ partials) {
-    constexpr int NC = CPLX ? 2 : 1;
-    const int vec = int(threadIdx.x) % B;
-    const double sc = sx ? sx[vec] : 1.0;
-    double q[kNQ] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
-        double hv[NC], xv[NC];
+    if (!A.last || !A.partials) return;
+    // lanes that share c_chunk hold the same vectors: reduce over the others
+    __shared__ double red[kWavesPerBlock][kNQ][kMaxNvec];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            hv[c] = sc * double(u[e * NC + c]);
-            xv[c] = sc * double(v[e * NC + c]);
+    for (int k = 0; k < kNQ; ++k)
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            double t = q[k][j];
+#pragma unroll
+            for (int off = CPR; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+            if (lane < CPR) red[wave][k][lane * VPT + j] = t;
         }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double o = a * hv[c] + b * xv[c];
-            u[e * NC + c] = S(o);
-            q[0] += xv[c] * xv[c];
-            q[1] += xv[c] * hv[c];
-            q[2] += hv[c] * hv[c];
-            q[3] += o * o;
-        }
-    }
-    if (!partials) return;
-    __shared__ double sh[kNQ][256];
-#pragma unroll
-    for (int k = 0; k < kNQ; ++k) sh[k][threadIdx.x] = q[k];
     __syncthreads();
-    if (int(threadIdx.x) < kNQ * B) {
-        const int k = threadIdx.x / B, bv = threadIdx.x % B;
+    if (tid < kNQ * B) {
+        const int k = tid / B, vec = tid % B;
         double acc = 0.0;
-        for (int t = bv; t < 256; t += B) acc += sh[k][t];
-        partials[size_t(blockIdx.x) * (kNQ * B) + threadIdx.x] = acc;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) acc += red[w][k][vec];
+        A.partials[size_t(blockIdx.x) * (kNQ * B) + tid] = acc;
     }
 }
 
@@ -1687,7 +1707,7 @@ static int launch_hv_s(const HvLaunch& L, hipStream_t st) {
 }
 
 // ---- dense-block product launch
-template <typename S, int RC, int M>
+template <typename S, bool CPLX, int RC, int M>
 static int launch_cma_stages(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
     using Sh = CmaShape<S, RC, M>;
     const hphi_ham* H = L.ham;
@@ -1698,37 +1718,46 @@ static int launch_cma_stages(const HvLaunch& L, const CmaPlan* P, hipStream_t st
         max_lds = 64 * 1024;
     if (lds > size_t(max_lds))
         return set_error(HPHI_EINVAL, "dense-block product: %d-bit clusters need %zu bytes of LDS", M, lds);
-    static const int occ = occupancy_blocks(cma_kernel<S, RC, M>);
+    static const int occ = occupancy_blocks(cma_kernel<S, CPLX, RC, M>);
     const int per_cu = occupancy_with_lds(occ, lds);
     CmaArgs A;
     A.v = L.v;
     A.u = L.u;
     A.nbits = H->basis->nbits;
     A.n_blocks = int64_t(1) << (A.nbits - M);
+    A.a = L.a;
+    A.b = L.b;
+    A.sx = L.sx;
+    A.partials = L.reduce_out ? H->d_partials : nullptr;
     int64_t g = int64_t(per_cu) * cu_count();
     if (g > A.n_blocks) g = A.n_blocks;
     g = ((g + 7) / 8) * 8;
+    if (g > kMaxGrid) g = kMaxGrid;
     const size_t D2 = size_t(1) << (2 * M);
     for (int c = 0; c < P->n_stage; ++c) {
         A.h = std::is_same<S, float>::value ? static_cast<const void*>(P->d_hf + c * D2)
                                             : static_cast<const void*>(P->d_hd + c * D2);
         A.bits = P->d_bits + size_t(c) * 64;
         A.first = c == 0 ? 1 : 0;
-        cma_kernel<S, RC, M><<<int(g), kBlock, lds, st>>>(A);
+        A.last = c == P->n_stage - 1 ? 1 : 0;
+        cma_kernel<S, CPLX, RC, M><<<int(g), kBlock, lds, st>>>(A);
         const int rc = check_hip(hipGetLastError(), "cma_kernel launch");
         if (rc) return rc;
     }
-    return HPHI_OK;
+    if (!L.reduce_out) return HPHI_OK;
+    constexpr int B = RC / (CPLX ? 2 : 1);
+    reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, int(g), kNQ * B, L.reduce_out, nullptr);
+    return check_hip(hipGetLastError(), "reduce launch");
 }
 
-template <typename S, int RC>
+template <typename S, bool CPLX, int RC>
 static int launch_cma_m(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
     switch (P->M) {
-        case 4: return launch_cma_stages<S, RC, 4>(L, P, st);
-        case 5: return launch_cma_stages<S, RC, 5>(L, P, st);
-        case 6: return launch_cma_stages<S, RC, 6>(L, P, st);
+        case 4: return launch_cma_stages<S, CPLX, RC, 4>(L, P, st);
+        case 5: return launch_cma_stages<S, CPLX, RC, 5>(L, P, st);
+        case 6: return launch_cma_stages<S, CPLX, RC, 6>(L, P, st);
         case 7:
-            if constexpr (sizeof(S) == 4) return launch_cma_stages<S, RC, 7>(L, P, st);
+            if constexpr (sizeof(S) == 4) return launch_cma_stages<S, CPLX, RC, 7>(L, P, st);
             break;
     }
     return set_error(HPHI_EINVAL, "dense-block product: cluster_bits %d not supported for this dtype", P->M);
@@ -1736,20 +1765,7 @@ static int launch_cma_m(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
 
 template <typename S, bool CPLX, int B>
 static int launch_cma_b(const HvLaunch& L, const CmaPlan* P, hipStream_t st) {
-    constexpr int RC = B * (CPLX ? 2 : 1);
-    int rc = launch_cma_m<S, RC>(L, P, st);
-    if (rc) return rc;
-    const int64_t n = L.ham->basis->dim * B;
-    int64_t g = (n + 255) / 256;
-    if (g > 2048) g = 2048;
-    g = (g / 8 > 0 ? g / 8 * 8 : 8);
-    double* partials = L.reduce_out ? L.ham->d_partials : nullptr;
-    cma_epilogue_kernel<S, CPLX, B><<<int(g), 256, 0, st>>>(static_cast<const S*>(L.v), static_cast<S*>(L.u), n,
-                                                           L.a, L.b, L.sx, partials);
-    rc = check_hip(hipGetLastError(), "cma_epilogue launch");
-    if (rc || !L.reduce_out) return rc;
-    reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(L.ham->d_partials, int(g), kNQ * B, L.reduce_out, nullptr);
-    return check_hip(hipGetLastError(), "reduce launch");
+    return launch_cma_m<S, CPLX, B * (CPLX ? 2 : 1)>(L, P, st);
 }
 
 template <typename S, bool CPLX>

@@ -74,6 +74,40 @@ def test_cma_matches_oracle(case, dt, nvec, m):
         assert abs(red[3, b] - np.linalg.norm(ref[:, b]) ** 2) <= 10 * tol * np.linalg.norm(ref[:, b]) ** 2
 
 
+@pytest.mark.parametrize("nvec", [2, 4, 8])
+@pytest.mark.parametrize("dt", ["f32", "c128"])
+def test_cma_other_vector_counts(dt, nvec):
+    """nvec 2, 4 and 8 (rows narrower than a 16-column tile, and 4- or 8-byte row copies)."""
+    torch_dt, tol = DTYPES[dt]
+    desc, mk = CASES["random_real10"]
+    terms = mk()
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(330, 330 + nvec)), dt.startswith("c"))
+    vd = torch.from_numpy(v).to(torch_dt).cuda()
+    u = hp.hphi_hv_cma(ham, vd, cluster_bits=5, b=0.25).cpu().numpy().astype(np.complex128)
+    x = vd.cpu().numpy().astype(np.complex128)
+    ref = oh.sparse_h(desc, terms, st) @ x + 0.25 * x
+    assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
+
+
+def test_cma_plan_covers_every_term():
+    """The cluster cover: M distinct sites per cluster, every term inside one cluster, and the
+    deterministic greedy gives the same cover on a second build."""
+    w = workload("kh_honeycomb24")
+    basis = hp.hphi_basis_build(w.basis)
+    ham = hp.hphi_ham_build(basis, w.terms)
+    for m in (4, 5, 6, 7):
+        cl = hp.hphi_hv_cma_plan(ham, m)
+        assert all(len(set(c)) == m and all(0 <= x < 24 for x in c) for c in cl)
+        for t in w.terms:
+            assert any(t.i in c and t.j in c for c in cl), (m, t.i, t.j)
+        again = hp.hphi_hv_cma_plan(hp.hphi_ham_build(basis, w.terms), m)
+        assert again == cl
+    assert len(hp.hphi_hv_cma_plan(ham, 6)) == 8
+
+
 def test_cma_equals_pull_product_in_fp64():
     """Both formulations of H v agree to rounding on the same FP64 input."""
     desc, mk = CASES["kh_honeycomb12"]
