@@ -92,6 +92,26 @@ def test_cma_other_vector_counts(dt, nvec):
     assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
 
 
+def test_cma_empty_and_diagonal_hamiltonians():
+    """No terms (H = 0: one all-zero cluster) and a diagonal-only H (fields along z, Ising bonds)."""
+    desc = BasisDesc("spin", 9)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), range(340, 344), True)
+    vd = torch.from_numpy(v).cuda()
+    diag = [L.Term(L.SPIN_BOND, i, (i + 1) % 9, (0, 0, 0, 0, 0, 0, 0, 0, 0.5 + 0.1 * i)) for i in range(9)] + \
+        [L.Term(L.SPIN_FIELD, i, -1, (0.0, 0.0, 0.2 * i)) for i in range(9)]
+    for terms in ([], diag):
+        basis = hp.hphi_basis_build(desc)
+        ham = hp.hphi_ham_build(basis, terms)
+        red = torch.empty(16, dtype=torch.float64, device="cuda")
+        u = hp.hphi_hv_cma(ham, vd, cluster_bits=4, a=2.0, b=-1.0, reduce=red).cpu().numpy()
+        hx = oh.sparse_h(desc, terms, st) @ v if terms else np.zeros_like(v)
+        ref = 2.0 * hx - v
+        assert np.linalg.norm(u - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.allclose(red.cpu().numpy().reshape(4, 4)[1], [np.vdot(v[:, b], hx[:, b]).real for b in range(4)],
+                           rtol=1e-12, atol=1e-12)
+
+
 def test_cma_plan_covers_every_term():
     """The cluster cover: M distinct sites per cluster, every term inside one cluster, and the
     deterministic greedy gives the same cover on a second build."""
