@@ -198,7 +198,7 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * size, overwritten) -- for full-space bases of 6..32 bits the windowed
  * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes,
  * gathering from v itself or from staged copies of v in each pass's row
- * order, or a single natural-order pass; lanes per row (nvec >= 8); resident blocks
+ * order, or a single natural-order pass; lanes per row (nvec >= 2); resident blocks
  * per CU, table placement -- and pins the fastest for this (ham, nvec, dtype): later
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different

@@ -1570,14 +1570,24 @@ template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
 static int launch_hv_l(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const bool w64 = L.ham->basis->nbits > 32;
     if (w64) {
-        if constexpr (B <= 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
+        if constexpr (B <= 4) {
+            if constexpr (B >= 2)
+                if (sc.lpr == 2) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, true>(L, sc, st);
+            if constexpr (B >= 4)
+                if (sc.lpr == 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, true>(L, sc, st);
+            return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
+        }
         return set_error(HPHI_EINVAL, "nvec > 4 needs a space of at most 32 bits");
     }
-    if constexpr (B >= 8) {
+    if constexpr (B >= 2) {
         switch (sc.lpr) {
             case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, false>(L, sc, st);
-            case 4: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false>(L, sc, st);
-            case 8: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 8, false>(L, sc, st);
+            case 4:
+                if constexpr (B >= 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false>(L, sc, st);
+                break;
+            case 8:
+                if constexpr (B >= 8) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 8, false>(L, sc, st);
+                break;
         }
     }
     return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, false>(L, sc, st);

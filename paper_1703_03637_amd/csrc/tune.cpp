@@ -38,7 +38,7 @@ Schedule default_schedule(int nvec) {
     s.window_kb = env_int("HPHI_L2_WINDOW_KB", s.window_kb);
     s.max_passes = env_int("HPHI_PASSES", s.max_passes);
     const int l = env_int("HPHI_LPR", 0);
-    if (nvec >= 8 && (l == 1 || l == 2 || l == 4 || l == 8)) s.lpr = l;
+    if ((l == 1 || l == 2 || l == 4 || l == 8) && l <= nvec) s.lpr = l;
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
     s.stage_tables = env_int("HPHI_STAGE_TABLES", s.stage_tables) ? 1 : 0;
     s.nt_streams = env_int("HPHI_NT_STREAMS", s.nt_streams) ? 1 : 0;
@@ -135,6 +135,7 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
     std::vector<Schedule> cands;
     std::vector<int> lprs = {1};
     if (nvec >= 8) lprs = {1, 2, 4, 8};
+    else if (nvec >= 2) lprs = nvec >= 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2};
     for (int bpc : {0, 4}) {
         for (int lpr : lprs) {
             Schedule s;

@@ -459,7 +459,7 @@ def test_hv_reduce_only_with_multipass_schedule(monkeypatch, window_kb):
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8])
 @pytest.mark.parametrize("case,windowed", [("spin_sz_dm", 0), ("kh_honeycomb12", 0), ("kh_honeycomb12", 1),
                                            ("spin_full_real", 2)])
-@pytest.mark.parametrize("nvec", [8, 16])
+@pytest.mark.parametrize("nvec", [2, 4, 8, 16])
 def test_hv_lanes_per_row(monkeypatch, lpr, case, windowed, nvec):
     """Rows split over 1, 2, 4 or 8 lanes (interleaved 16-byte chunks): output, per-vector scales and
     per-vector reductions all land on the right vector, for every storage type."""

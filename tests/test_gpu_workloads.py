@@ -101,6 +101,34 @@ def test_w64_small_sectors_match_oracle(name):
         assert np.all(np.abs(u - ref) <= 1e-12 * bound + 1e-300)
 
 
+@pytest.mark.parametrize("lpr", [2, 4])
+@pytest.mark.parametrize("name", ["kagome36_2sz32", "hubbard18_1u1d"])
+def test_w64_lanes_per_row(monkeypatch, name, lpr):
+    """36-bit sector products with each row's 2 or 4 vectors split over lanes, FP64 and complex64."""
+    monkeypatch.setenv("HPHI_LPR", str(lpr))
+    print(f"[gpu] w64 lanes per row {name} lpr={lpr}", flush=True)
+    desc, terms, states = _w64_case(name)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    H = oh.sparse_h(desc, terms, basis_states=states)
+    for nvec in (2, 4):
+        if lpr > nvec:
+            continue
+        v = uniform_vectors(basis.dim, list(range(50, 50 + nvec)), True)
+        sx = torch.linspace(0.5, 1.5, nvec, dtype=torch.float64, device="cuda")
+        for dt, tol in ((torch.complex128, 1e-12), (torch.complex64, 2e-6)):
+            vd = torch.from_numpy(v).to(dt).cuda()
+            red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+            u = hp.hphi_hv(ham, vd, in_scale=sx, reduce=red).cpu().numpy().astype(np.complex128)
+            x = vd.cpu().numpy().astype(np.complex128) * sx.cpu().numpy()[None, :]
+            ref = H @ x
+            assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref), (nvec, dt)
+            red = red.cpu().numpy().reshape(4, nvec)
+            for b in range(nvec):
+                assert abs(red[1, b] - np.vdot(x[:, b], ref[:, b]).real) <= 10 * tol * np.linalg.norm(x[:, b]) * \
+                    np.linalg.norm(ref[:, b]), (nvec, dt, b)
+
+
 def _row_abs_sum_bound(terms, particle):
     """Upper bound on max_s sum_t |<s|H|t>|: each term's own maximum absolute row sum, from its
     dense matrix on the sites it touches (oracle)."""
