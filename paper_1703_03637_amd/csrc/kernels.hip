@@ -358,8 +358,8 @@ __device__ __forceinline__ void stage_to_lds(void* dst, const void* src, size_t 
 }
 
 // Bytes of LDS the single-pass product stages: the pattern table, and on a
-// sector basis the low split rank table.  Above kLdsStageBytes everything is
-// read from global memory instead (GTAB).
+// sector basis the low split rank table.  A table that does not fit under
+// kLdsStageBytes is read from global memory instead (TAB).
 constexpr size_t kLdsStageBytes = 64 * 1024;
 
 // Body of the single-pass product for the block `blk` of `nblk` (a multiple
@@ -367,9 +367,10 @@ constexpr size_t kLdsStageBytes = 64 * 1024;
 // S: storage scalar, CPLX: complex vectors, CCOEF: complex coefficients,
 // SECTOR: split-table rank, B: interleaved vectors per row, LPR: lanes per
 // row (each lane owns B/LPR of the vectors, in interleaved chunks),
-// W64: configurations above 32 bits, GTAB: tables read from global memory
-// (else staged in LDS).
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+// W64: configurations above 32 bits, TAB: table placement (0: pattern and
+// low rank tables staged in LDS, 1: both read from global memory, 2: pattern
+// table in LDS, low rank table from global memory).
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
 __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const int nblk) {
     using ST = typename StateT<W64>::type;
     constexpr int NC = CPLX ? 2 : 1;
@@ -401,7 +402,7 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     const uint32_t* jlo = nullptr;
     typedef const __attribute__((address_space(4))) int64_t ConstI64;
     const ConstI64* jhi = (const ConstI64*)(bs.j_hi);
-    if constexpr (GTAB) {
+    if constexpr (TAB == 1) {
         tab = A.ptab;
         if constexpr (SECTOR) jlo = bs.j_lo;
     } else {
@@ -409,10 +410,14 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
         stage_to_lds(lt, A.ptab, size_t(n_ops) * 16 * sizeof(double));
         tab = lt;
         if constexpr (SECTOR) {
-            uint32_t* ll = reinterpret_cast<uint32_t*>(lt + n_ops * 16);
-            const int n_lo = 1 << bs.b_lo;
-            stage_to_lds(ll, bs.j_lo, size_t(n_lo) * 4);
-            jlo = ll;
+            if constexpr (TAB == 0) {
+                uint32_t* ll = reinterpret_cast<uint32_t*>(lt + n_ops * 16);
+                const int n_lo = 1 << bs.b_lo;
+                stage_to_lds(ll, bs.j_lo, size_t(n_lo) * 4);
+                jlo = ll;
+            } else {
+                jlo = bs.j_lo;   // too large for LDS: read through the caches
+            }
         }
         __syncthreads();
     }
@@ -513,15 +518,22 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                         live = live && base_hi >= 0;
                         // low part: the row's own rank among its class when the
                         // operator leaves the low half alone, else the table
-                        const int64_t part_lo =
-                            xm_lo ? int64_t(jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo]) : row - hrow;
-                        idx = base_hi + part_lo;
+                        uint32_t part_lo = uint32_t(row - hrow);
+                        if (xm_lo) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
+                        idx = base_hi + int64_t(part_lo);
                     } else {
                         idx = int64_t(s ^ ST(xmask));
                     }
                     crk[k] = live ? cr : 0.0;
                     cik[k] = live ? ci : 0.0;
                     ik[k] = idx;
+                }
+                if constexpr (SECTOR) {
+                    // the four target indices are complete here (one wait for
+                    // the rank loads), so the gathers below issue back to back
+                    // instead of each waiting behind the previous one
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(ik[k]));
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -612,22 +624,22 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     }
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
 __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
-    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>(A, int(blockIdx.x), int(gridDim.x));
+    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>(A, int(blockIdx.x), int(gridDim.x));
 }
 
 // Several problems in one launch (uneven sector sizes): problem p owns the
 // blocks begin[p] .. begin[p+1]-1 (multiples of 8, so block & 7 still
 // names the XCD) and its own partials.
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
 __global__ __launch_bounds__(kBlock) void hv_multi_kernel(const HvArgs* __restrict__ probs,
                                                           const int* __restrict__ begin, int n_probs) {
     int p = 0;
     for (int q = 1; q < n_probs; ++q)
         if (int(blockIdx.x) >= begin[q]) p = q;
     const HvArgs A = probs[p];
-    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>(A, int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
+    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>(A, int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1525,10 +1537,10 @@ static int occupancy_with_lds(int occ, size_t lds) {
     return by_lds < occ ? (by_lds < 1 ? 1 : by_lds) : occ;
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool GTAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
 static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStream_t st) {
     const hphi_ham* H = L.ham;
-    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB>);
+    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>);
     const int grid = make_grid(occupancy_with_lds(occ, lds), sc, H->basis->dev.n_tiles);
     HvArgs A;
     A.bs = H->basis->dev;
@@ -1544,7 +1556,7 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
-    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, GTAB><<<grid, kBlock, lds, st>>>(A);
+    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB><<<grid, kBlock, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
     if (L.reduce_out) {
@@ -1554,16 +1566,22 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     return rc;
 }
 
+// Table placement: 0 = pattern table and low rank table in LDS, 1 = both read
+// from global memory, 2 = pattern table in LDS and the (large) low rank
+// table from global memory.
 template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
 static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
-    if constexpr (W64) {
-        return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
-    } else {
+    const size_t ptab = size_t(L.ham->n_ops_pad) * 16 * sizeof(double);
+    if constexpr (!W64) {
         const size_t lds = hv_stage_bytes(L.ham, SECTOR);
         if (sc.stage_tables && lds <= kLdsStageBytes)
-            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, false>(L, sc, lds, st);
-        return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, true>(L, sc, 0, st);
+            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 0>(L, sc, lds, st);
     }
+    if constexpr (SECTOR) {
+        if (sc.stage_tables && ptab <= kLdsStageBytes)
+            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 2>(L, sc, ptab, st);
+    }
+    return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 1>(L, sc, 0, st);
 }
 
 template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
@@ -1928,9 +1946,9 @@ int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const
 
 // ---------------------------------------------------------------- batched
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, bool W64, bool GTAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, bool W64, int TAB>
 static int hv_multi_go(const MultiPlan& P, hipStream_t st) {
-    hv_multi_kernel<S, CPLX, CCOEF, SECTOR, 1, 1, W64, GTAB><<<P.grid, kBlock, P.lds, st>>>(
+    hv_multi_kernel<S, CPLX, CCOEF, SECTOR, 1, 1, W64, TAB><<<P.grid, kBlock, P.lds, st>>>(
         static_cast<const HvArgs*>(P.d_args), P.d_begin, P.n);
     int rc = check_hip(hipGetLastError(), "hv_multi launch");
     if (rc) return rc;
@@ -1941,14 +1959,14 @@ static int hv_multi_go(const MultiPlan& P, hipStream_t st) {
 template <typename S, bool CPLX, bool CCOEF>
 static int hv_multi_s(const MultiPlan& P, hipStream_t st) {
     if (P.w64) {
-        if (P.sector) return hv_multi_go<S, CPLX, CCOEF, true, true, true>(P, st);
-        return hv_multi_go<S, CPLX, CCOEF, false, true, true>(P, st);
+        if (P.sector) return hv_multi_go<S, CPLX, CCOEF, true, true, 1>(P, st);
+        return hv_multi_go<S, CPLX, CCOEF, false, true, 1>(P, st);
     }
     if (P.sector)
-        return P.gtab ? hv_multi_go<S, CPLX, CCOEF, true, false, true>(P, st)
-                      : hv_multi_go<S, CPLX, CCOEF, true, false, false>(P, st);
-    return P.gtab ? hv_multi_go<S, CPLX, CCOEF, false, false, true>(P, st)
-                  : hv_multi_go<S, CPLX, CCOEF, false, false, false>(P, st);
+        return P.gtab ? hv_multi_go<S, CPLX, CCOEF, true, false, 1>(P, st)
+                      : hv_multi_go<S, CPLX, CCOEF, true, false, 0>(P, st);
+    return P.gtab ? hv_multi_go<S, CPLX, CCOEF, false, false, 1>(P, st)
+                  : hv_multi_go<S, CPLX, CCOEF, false, false, 0>(P, st);
 }
 
 int hv_multi_launch(const MultiPlan& P, hipStream_t st) {
