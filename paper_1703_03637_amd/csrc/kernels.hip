@@ -31,9 +31,12 @@
 namespace hphi {
 namespace {
 
+constexpr int ilog2(int b) { return b <= 1 ? 0 : 1 + ilog2(b / 2); }
+
 template <int B>
 struct Log2 {
-    static constexpr int value = B == 1 ? 0 : B == 2 ? 1 : B == 4 ? 2 : B == 8 ? 3 : 4;
+    static_assert(B > 0 && (B & (B - 1)) == 0, "power of two");
+    static constexpr int value = ilog2(B);
 };
 
 template <typename T>
