@@ -60,7 +60,9 @@ struct Schedule {
 // at most 32 bits), FP64 values.  Element for row
 // pattern p = bit(s,bi) | bit(s,bj) << 1: (c[p] + i ci[p]) times the sign
 // (-1)^popcount(s & sm); diagonal part d[p].  xm == 0 marks a padding or
-// diagonal-only entry.
+// diagonal-only entry.  lq is the flip mask in the pass's processing-index
+// bits when the partner row lies in the same 64-row tile (lq < 64), else
+// ~0u: a wavefront that holds both rows exchanges them between lanes.
 template <typename T>
 struct alignas(128) KOp {
     uint32_t xm;
@@ -70,6 +72,7 @@ struct alignas(128) KOp {
     T c[4];
     T ci[4];
     T d[4];
+    uint32_t lq;
 };
 
 // Pass plan of the windowed full-space product.  Each pass applies the

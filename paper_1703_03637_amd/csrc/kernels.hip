@@ -185,6 +185,54 @@ __device__ __forceinline__ void store_lane_nt(S* __restrict__ base, int64_t row,
         put_chunk_nt<Ly::CB>(p + j * LPR * Ly::CB, reinterpret_cast<const char*>(in) + j * Ly::CB);
 }
 
+// Values of another lane of the wavefront (byte address 4 * lane); every
+// lane of the wavefront must take part.
+template <typename S, int NE>
+__device__ __forceinline__ void exchange_lane(const S (&x)[NE], int addr, S (&out)[NE]) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        if constexpr (sizeof(S) == 4) {
+            out[e] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x[e])));
+        } else {
+            const long long w = __double_as_longlong(x[e]);
+            const int lo = __builtin_amdgcn_ds_bpermute(addr, int(w));
+            const int hi = __builtin_amdgcn_ds_bpermute(addr, int(w >> 32));
+            out[e] = __longlong_as_double(static_cast<long long>(static_cast<unsigned>(lo)) |
+                                          (static_cast<long long>(hi) << 32));
+        }
+    }
+}
+
+// Whether the windowed product keeps a wavefront's 64-row tile of v in LDS
+// (8 lanes per row measured slower with it).
+__host__ __device__ constexpr bool tile_in_lds(int row_bytes, int lpr) { return 64 * row_bytes <= 8192 && lpr <= 4; }
+
+// A wavefront's 64-row tile of v in LDS, rows in the lane layout of
+// memory; odd rows swap the two halves of their chunks, so that lanes
+// reading consecutive rows spread over all banks.
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ int tile_chunk(int r, int c) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    constexpr int NCR = Ly::RB / Ly::CB;
+    return r * Ly::RB + (NCR >= 2 ? (c ^ ((r & 1) * (NCR / 2))) : c) * Ly::CB;
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void tile_put(char* tb, int r, int sub, const S (&in)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        put_chunk<Ly::CB>(tb + tile_chunk<S, NE, LPR>(r, j * LPR + sub), reinterpret_cast<const char*>(in) + j * Ly::CB);
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void tile_get(const char* tb, int r, int sub, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, tb + tile_chunk<S, NE, LPR>(r, j * LPR + sub));
+}
+
 template <typename S, int NE, int LPR>
 __device__ __forceinline__ void load_lane(const S* __restrict__ base, int64_t row, int sub, S (&out)[NE]) {
     using Ly = LaneLayout<S, NE, LPR>;
@@ -693,6 +741,14 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     constexpr int RPW = 64 / LPR;
     constexpr int LOGV = Log2<VPL>::value;
     constexpr int LOGL = Log2<LPR>::value;
+    constexpr int LOGR = 6 - LOGL;          // row bits held by one wavefront pass
+    // the wavefront's tile of v in LDS (rows of at most 128 bytes, at most 4
+    // lanes per row): partners anywhere in the tile are read from there;
+    // otherwise only partners within the rows of one wavefront pass are
+    // exchanged between lanes
+    constexpr int TRB = LaneLayout<S, NE, LPR>::RB;
+    constexpr bool TL = tile_in_lds(TRB, LPR);
+    constexpr int LOGT = TL ? 6 : LOGR;
     static_assert(VPL * LPR == B, "LPR must divide B");
     if (A.stop && *A.stop) return;
     const bool first = (A.mode & 1) != 0, last = (A.mode & 2) != 0;
@@ -748,6 +804,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
         }
     }
     __syncthreads();
+    char* tb = reinterpret_cast<char*>(lds_dyn) + size_t(n_ops) * 4 * TE * sizeof(double) + size_t(wave) * 64 * TRB;
 
     // gathered rows stay live across operators: a lane whose element is zero
     // skips its load and multiplies the previous (finite) values by 0.0
@@ -766,6 +823,26 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 s_tile |= 1u << c;
                 if (stg) qn_tile |= 1u << inv_next[c];
             }
+        if constexpr (TL) {
+            // the tile's rows into LDS (LDS accesses of a wavefront complete in
+            // order, so the reads of the previous tile are done)
+            alignas(16) S tv[LPR][NE];
+#pragma unroll
+            for (int pass = 0; pass < LPR; ++pass) {
+                const int r = pass * RPW + rlane;
+                uint32_t s = s_tile;
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    if ((r >> k) & 1) s |= 1u << perm[k];
+                const uint32_t base = gq ? ((uint32_t(tile) << 6) | uint32_t(r)) : s;
+                load_lane<S, NE, LPR>(v, int64_t(base), sub, tv[pass]);
+            }
+#pragma unroll
+            for (int pass = 0; pass < LPR; ++pass) tile_put<S, NE, LPR>(tb, pass * RPW + rlane, sub, tv[pass]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll 1
         for (int pass = 0; pass < LPR; ++pass) {
             const int r = pass * RPW + rlane;      // position within the 64-row tile
@@ -780,6 +857,11 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             // index of this row in the gather source
             const uint32_t base = gq ? ((uint32_t(tile) << 6) | uint32_t(r)) : s;
 
+            // the row's own values first: partners held by this wavefront are
+            // taken from them through lane exchanges, not memory
+            alignas(16) S vr[NE];
+            if constexpr (TL) tile_get<S, NE, LPR>(tb, r, sub, vr);
+            else load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
             double acc[NE];
 #pragma unroll
             for (int e = 0; e < NE; ++e) acc[e] = 0.0;
@@ -789,10 +871,15 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             for (int o = 0; o < n_ops; o += 4) {
                 double crk[4], cik[4];
                 uint32_t tk[4];
+                bool lk[4];   // partner held by this wavefront (uniform)
+                int xa[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const ConstKOp& rec = kops[A.kop_begin + o + k];
-                    const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj;
+                    const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj, lq = rec.lq;
+                    lk[k] = (lq >> LOGT) == 0u;
+                    // partner: tile row r ^ lq, or the byte address of its lane
+                    xa[k] = TL ? int(lq & 63u) : (lane ^ int(lq << LOGL)) << 2;
                     const uint32_t pat = __builtin_amdgcn_ubfe(s, bi, 1u) | (__builtin_amdgcn_ubfe(s, bj, 1u) << 1);
                     const double* te = lds_dyn + ((o + k) * 4 + int(pat)) * TE;
                     double cr = te[0], ci = 0.0;
@@ -814,7 +901,11 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
-                    if (act) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
+                    if (lk[k]) {
+                        if constexpr (TL) tile_get<S, NE, LPR>(tb, r ^ int(xa[k]), sub, g[k]);
+                        else exchange_lane<S, NE>(vr, xa[k], g[k]);
+                    }
+                    else if (act) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -837,8 +928,6 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 }
             }
 
-            alignas(16) S vr[NE];
-            load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
             if (stg) {
                 if constexpr (NT) store_lane_nt<S, NE, LPR>(stg, int64_t(qn), sub, vr);
                 else store_lane<S, NE, LPR>(stg, int64_t(qn), sub, vr);
@@ -1632,7 +1721,16 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
                         hipStream_t st) {
     const hphi_ham* H = L.ham;
     static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR, NT>);
-    const int grid = make_grid(occ, sc, H->basis->dev.n_tiles);
+    // dynamic LDS: the pass's pattern table, then one row tile per wavefront
+    constexpr int NE = (B / LPR) * (CPLX ? 2 : 1);
+    constexpr int TRB = LaneLayout<S, NE, LPR>::RB;
+    constexpr size_t tile_lds = tile_in_lds(TRB, LPR) ? size_t(kWavesPerBlock) * 64 * TRB : 0;
+    auto lds_of = [&](int p) {
+        return size_t(P->kop_begin[p + 1] - P->kop_begin[p]) * 4 * (CCOEF ? 4 : 2) * sizeof(double) + tile_lds;
+    };
+    size_t lds_max = 0;
+    for (int p = 0; p < P->n_pass; ++p) lds_max = std::max(lds_max, lds_of(p));
+    const int grid = make_grid(occupancy_with_lds(occ, lds_max), sc, H->basis->dev.n_tiles);
     HvwArgs A;
     A.nbits = H->basis->nbits;
     A.n_tiles = H->basis->dev.n_tiles;
@@ -1658,8 +1756,7 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
         A.g_q = (staged && p > 0) ? 1 : 0;
         A.stage = next ? stage[p & 1] : nullptr;
         A.inv_next = next ? P->d_inv + size_t(p + 1) * 64 : nullptr;
-        const size_t lds = size_t(A.kop_end - A.kop_begin) * 4 * (CCOEF ? 4 : 2) * sizeof(double);
-        hvw_kernel<S, CPLX, CCOEF, B, LPR, NT><<<grid, kBlock, lds, st>>>(A);
+        hvw_kernel<S, CPLX, CCOEF, B, LPR, NT><<<grid, kBlock, lds_of(p), st>>>(A);
         int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
         if (rc) return rc;
     }
@@ -1702,9 +1799,13 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     // several passes carry partial sums through u: they need a real output
     // buffer that is not also an input
     if (P->n_pass > 1 && (!L.u || L.y)) return 1;
-    // the pattern table of a pass lives in LDS: at most kMaxPassOps operators
-    for (int p = 0; p < P->n_pass; ++p)
-        if (P->kop_begin[p + 1] - P->kop_begin[p] > kMaxPassOps) return 1;
+    // the pattern table of a pass lives in LDS: at most kMaxPassOps operators,
+    // and with the row tiles (for rows of at most 128 bytes) within 160 KB
+    const size_t tile_lds = tile_in_lds(row_bytes, 1) ? size_t(kWavesPerBlock) * 64 * row_bytes : 0;
+    for (int p = 0; p < P->n_pass; ++p) {
+        const int n = P->kop_begin[p + 1] - P->kop_begin[p];
+        if (n > kMaxPassOps || size_t(n) * 4 * (CCOEF ? 4 : 2) * sizeof(double) + tile_lds > 160 * 1024) return 1;
+    }
     bool staged = sc.windowed == 2 && P->n_pass > 1;
     void* stage[2] = {nullptr, nullptr};
     if (staged) {

@@ -203,6 +203,14 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
     P->inv.assign(size_t(P->n_pass) * 64, 0);
     for (int p = 0; p < P->n_pass; ++p)
         for (int k = 0; k < nbits; ++k) P->inv[size_t(p) * 64 + P->perm[size_t(p) * 64 + k]] = k;
+    // partners inside the 64-row tile, in processing-index bits
+    for (int p = 0; p < P->n_pass; ++p)
+        for (int o = P->kop_begin[p]; o < P->kop_begin[p + 1]; ++o) {
+            uint32_t m = 0;
+            for (int b = 0; b < nbits; ++b)
+                if ((k64[o].xm >> b) & 1u) m |= 1u << P->inv[size_t(p) * 64 + b];
+            k64[o].lq = (k64[o].xm != 0 && m < 64u) ? m : ~0u;
+        }
     std::vector<KOp<double>> kq = k64;
     for (int p = 1; p < P->n_pass; ++p)
         for (int o = P->kop_begin[p]; o < P->kop_begin[p + 1]; ++o) {

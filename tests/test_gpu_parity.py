@@ -500,6 +500,51 @@ def test_hv_lanes_per_row(monkeypatch, lpr, case, windowed, nvec):
                 assert abs(red[q, k] - want[q]) <= 10 * tol * scale_k[q] + 1e-300, (dt, q, k)
 
 
+_TILE_PAIRS = [(0, 1), (1, 2), (2, 3), (0, 2), (1, 3), (0, 3),      # flips inside 16 rows
+               (3, 4), (4, 5), (2, 4), (3, 5), (0, 5), (1, 4),      # inside a 64-row tile only
+               (5, 6), (6, 7), (7, 8), (8, 9), (9, 10), (10, 11), (0, 11), (2, 9)]
+
+
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8])
+@pytest.mark.parametrize("windowed,passes", [(1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("dt,nvec", [(torch.complex64, 16), (torch.complex128, 8), (torch.complex128, 16),
+                                     (torch.float32, 16), (torch.float64, 4)])
+def test_hv_windowed_tile_partners(monkeypatch, lpr, windowed, passes, dt, nvec):
+    """Windowed product with partners in every place a row can find them: within the rows one
+    wavefront pass holds (lane exchange), elsewhere in its 64-row tile (LDS tile for rows of at
+    most 128 bytes and at most 4 lanes per row) and outside the tile (memory gathers); one window,
+    and two passes with and without staged copies."""
+    print(f"[gpu] windowed tile partners lpr={lpr} windowed={windowed} passes={passes} dt={dt} nvec={nvec}",
+          flush=True)
+    monkeypatch.setenv("HPHI_LPR", str(lpr))
+    monkeypatch.setenv("HPHI_WINDOWED", str(windowed))
+    monkeypatch.setenv("HPHI_PASSES", str(passes))
+    monkeypatch.setenv("HPHI_L2_WINDOW_KB", "65536" if passes == 1 else "4")
+    desc = BasisDesc("spin", 12)
+    terms = [L.xxz_bond(i, j, 0.6 + 0.05 * k, -0.4 + 0.1 * k) for k, (i, j) in enumerate(_TILE_PAIRS)]
+    terms += L.random_spin_terms(12, 4, 31, conserve_sz=False, fields=True, real=True)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    H = oh.sparse_h(desc, terms, st)
+    cplx = dt in (torch.complex128, torch.complex64)
+    tol = 1e-12 if dt in (torch.complex128, torch.float64) else 3e-6
+    v = uniform_vectors(len(st), list(range(300, 300 + nvec)), cplx)
+    vd = _to_dev(v if cplx else v.real, dt)
+    vin = vd.cpu().numpy().astype(np.complex128)
+    red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+    a, b = 0.5, 0.25
+    u = hp.hphi_hv(ham, vd, a=a, b=b, reduce=red).cpu().numpy().astype(np.complex128)
+    hx = H @ vin
+    ref = a * hx + b * vin
+    for k in range(nvec):
+        assert np.linalg.norm(u[:, k] - ref[:, k]) <= tol * np.linalg.norm(ref[:, k]), k
+    red = red.cpu().numpy().reshape(4, nvec)
+    for k in range(nvec):
+        want = np.vdot(vin[:, k], hx[:, k]).real
+        assert abs(red[1, k] - want) <= 10 * tol * np.linalg.norm(vin[:, k]) * np.linalg.norm(hx[:, k]), k
+
+
 # ------------------------------------------------------- batched Lanczos
 
 def _tri12_sectors(dtype, n_iter, use_graph=True, seeds0=500):
