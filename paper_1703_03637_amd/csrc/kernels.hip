@@ -857,8 +857,9 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             // index of this row in the gather source
             const uint32_t base = gq ? ((uint32_t(tile) << 6) | uint32_t(r)) : s;
 
-            // the row's own values first: partners held by this wavefront are
-            // taken from them through lane exchanges, not memory
+            // the row's own values first (from the LDS tile, or from memory;
+            // without the tile, partners within this wavefront pass are
+            // exchanged from them between lanes)
             alignas(16) S vr[NE];
             if constexpr (TL) tile_get<S, NE, LPR>(tb, r, sub, vr);
             else load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
@@ -871,7 +872,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             for (int o = 0; o < n_ops; o += 4) {
                 double crk[4], cik[4];
                 uint32_t tk[4];
-                bool lk[4];   // partner held by this wavefront (uniform)
+                bool lk[4];   // partner on chip: in the LDS tile, or in this wavefront pass (uniform)
                 int xa[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
