@@ -506,23 +506,24 @@ _TILE_PAIRS = [(0, 1), (1, 2), (2, 3), (0, 2), (1, 3), (0, 3),      # flips insi
 
 
 @pytest.mark.parametrize("lpr", [1, 2, 4, 8])
-@pytest.mark.parametrize("windowed,passes", [(1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("n_sites,windowed,passes", [(12, 1, 1), (12, 1, 2), (12, 2, 2), (7, 1, 1), (7, 2, 2)])
 @pytest.mark.parametrize("dt,nvec", [(torch.complex64, 16), (torch.complex128, 8), (torch.complex128, 16),
                                      (torch.float32, 16), (torch.float64, 4)])
-def test_hv_windowed_tile_partners(monkeypatch, lpr, windowed, passes, dt, nvec):
+def test_hv_windowed_tile_partners(monkeypatch, lpr, n_sites, windowed, passes, dt, nvec):
     """Windowed product with partners in every place a row can find them: within the rows one
     wavefront pass holds (lane exchange), elsewhere in its 64-row tile (LDS tile for rows of at
     most 128 bytes and at most 4 lanes per row) and outside the tile (memory gathers); one window,
-    and two passes with and without staged copies."""
-    print(f"[gpu] windowed tile partners lpr={lpr} windowed={windowed} passes={passes} dt={dt} nvec={nvec}",
-          flush=True)
+    and two passes with and without staged copies; 7 sites is two tiles."""
+    print(f"[gpu] windowed tile partners lpr={lpr} n_sites={n_sites} windowed={windowed} passes={passes} "
+          f"dt={dt} nvec={nvec}", flush=True)
     monkeypatch.setenv("HPHI_LPR", str(lpr))
     monkeypatch.setenv("HPHI_WINDOWED", str(windowed))
     monkeypatch.setenv("HPHI_PASSES", str(passes))
     monkeypatch.setenv("HPHI_L2_WINDOW_KB", "65536" if passes == 1 else "4")
-    desc = BasisDesc("spin", 12)
-    terms = [L.xxz_bond(i, j, 0.6 + 0.05 * k, -0.4 + 0.1 * k) for k, (i, j) in enumerate(_TILE_PAIRS)]
-    terms += L.random_spin_terms(12, 4, 31, conserve_sz=False, fields=True, real=True)
+    desc = BasisDesc("spin", n_sites)
+    pairs = [(i, j) for (i, j) in _TILE_PAIRS if i < n_sites and j < n_sites]
+    terms = [L.xxz_bond(i, j, 0.6 + 0.05 * k, -0.4 + 0.1 * k) for k, (i, j) in enumerate(pairs)]
+    terms += L.random_spin_terms(n_sites, 4, 31, conserve_sz=False, fields=True, real=True)
     basis = hp.hphi_basis_build(desc)
     ham = hp.hphi_ham_build(basis, terms)
     st = ob.states(desc)
