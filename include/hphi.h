@@ -345,8 +345,10 @@ int hphi_cg_refine(const hphi_ham* ham, void* x, int32_t dtype, double e_approx,
  * observables of TPQ states and eigenvectors, e.g. the doublon density of
  * Sec. 5.1).  O is given as a term list built into its own hphi_ham on the
  * same basis: the Hubbard-U kind with U = 1 counts doublons, a HOP term
- * measures c+_a c_b + h.c. (2 Re <c+_a c_b>; t = i gives 2 Im), DENS
- * measures n_a n_b, a spin bond S^a_i S^b_j.  psi: device, dim*nvec
+ * t c+_a c_b + conj(t) c+_b c_a measures 2 Re <c+_a c_b> at t = 1 and
+ * -2 Im <c+_a c_b> at t = i (together the one-body Green's function), DENS
+ * measures n_a n_b, a spin bond S^a_i S^b_j (the density and spin two-body
+ * correlations).  psi: device, dim*nvec
  * elements of dtype, interleaved as for hphi_hv.  out: device [2 * nvec]
  * (FP64): out[b] = Re<psi_b|O|psi_b> / <psi_b|psi_b>, out[nvec + b] =
  * <psi_b|psi_b>.  Uses the product kernels in reduce-only mode (no output

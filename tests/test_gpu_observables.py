@@ -56,6 +56,38 @@ def test_expect_matches_oracle(nvec):
             assert abs(got[b] - want) <= 1e-12 * max(1.0, abs(want)), (name, b)
 
 
+def _green_direct(desc, st, x, a, b):
+    """<x| c+_a c_b |x> / <x|x> with the operator product applied to each basis state."""
+    coef, tgt = oh.apply_product([lambda y: oh.create(a, y), lambda y: oh.annihilate(b, y)], st)
+    y = np.zeros_like(x)
+    hit = coef != 0
+    idx = np.searchsorted(st, tgt[hit])
+    assert np.all(st[idx] == tgt[hit])
+    np.add.at(y, idx, coef[hit] * x[hit])
+    return np.vdot(x, y) / np.vdot(x, x).real
+
+
+def test_one_body_green_function_from_two_hermitian_forms():
+    """G_ab = <c+_a c_b> of complex states, assembled from the t = 1 and t = i hopping forms, against
+    the operator product applied directly (pins the sign of the imaginary part)."""
+    print("[gpu] one-body Green's function", flush=True)
+    w = workload("hubbard8_tpq")
+    n, bonds, _ = L.square_supercell((2, 2), (-2, 2))
+    basis = hp.hphi_basis_build(w.basis)
+    st = ob.states(w.basis)
+    v = uniform_vectors(len(st), [81, 82], True)
+    vd = _to_dev(v, torch.complex128)
+    pairs = [(2 * bonds[0][0], 2 * bonds[0][1]), (2 * bonds[1][0] + 1, 2 * bonds[1][1] + 1), (0, 6), (7, 3)]
+    for a, b in pairs:
+        re2 = hp.hphi_expect(hp.hphi_ham_build(basis, [L.Term(L.HOP, a, b, (1.0, 0.0))]), vd).cpu().numpy()
+        im2 = hp.hphi_expect(hp.hphi_ham_build(basis, [L.Term(L.HOP, a, b, (0.0, 1.0))]), vd).cpu().numpy()
+        for k in range(2):
+            g = complex(re2[k], -im2[k]) / 2
+            want = _green_direct(w.basis, st, v[:, k], a, b)
+            assert abs(want.imag) > 1e-6, "the state must give a complex G"
+            assert abs(g - want) <= 1e-12, (a, b, k, g, want)
+
+
 def test_tpq_doublon_matches_exact_mtpq_and_canonical_ensemble():
     """20 TPQ samples (5 batched launches of 4) on the 8-site Hubbard cluster: at every step the
     sample-averaged doublon density per site matches the closed-form mTPQ average
