@@ -42,10 +42,9 @@ DTYPES = {"f32": (torch.float32, 3e-6), "f64": (torch.float64, 1e-12),
 @pytest.mark.parametrize("dt", list(DTYPES))
 @pytest.mark.parametrize("case", list(CASES))
 def test_cma_matches_oracle(case, dt, nvec, m):
-    """Output, input scale, a/b and the four per-vector FP64 reductions, against the oracle."""
+    """Output, input scale, a/b and the four per-vector FP64 reductions, against the oracle.
+    FP64 storage takes clusters of at most 6 bits: 7 is rejected before any launch."""
     torch_dt, tol = DTYPES[dt]
-    if m == 7 and torch_dt in (torch.float64, torch.complex128):
-        pytest.skip("FP64 blocks allow at most 6 bits (LDS capacity)")
     print(f"[gpu] cma case={case} dt={dt} nvec={nvec} m={m}", flush=True)
     desc, mk = CASES[case]
     terms = mk()
@@ -59,6 +58,11 @@ def test_cma_matches_oracle(case, dt, nvec, m):
         vd = vd.reshape(-1)
     sx = torch.linspace(0.5, 1.5, nvec, dtype=torch.float64, device="cuda")
     red = torch.empty(4 * nvec, dtype=torch.float64, device="cuda")
+    if m == 7 and torch_dt in (torch.float64, torch.complex128):
+        with pytest.raises(hp.HphiError) as e:
+            hp.hphi_hv_cma(ham, vd, cluster_bits=m, a=0.75, b=-0.5, in_scale=sx, reduce=red)
+        assert e.value.code == -1
+        return
     u = hp.hphi_hv_cma(ham, vd, cluster_bits=m, a=0.75, b=-0.5, in_scale=sx, reduce=red)
     u = u.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
     x = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec) * sx.cpu().numpy()[None, :]
