@@ -568,9 +568,17 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                         const int64_t base_hi = xm_hi ? jhi[hval ^ xm_hi] : hrow;
                         live = live && base_hi >= 0;
                         // low part: the row's own rank among its class when the
-                        // operator leaves the low half alone, else the table
+                        // operator leaves the low half alone, else the table;
+                        // a table in global memory is read only by lanes whose
+                        // element is nonzero (from LDS, the branch costs more
+                        // than the reads it saves)
                         uint32_t part_lo = uint32_t(row - hrow);
-                        if (xm_lo) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
+                        if constexpr (TAB == 0) {
+                            if (xm_lo) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
+                        } else {
+                            const bool nz = CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0);
+                            if (xm_lo && live && nz) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
+                        }
                         idx = base_hi + int64_t(part_lo);
                     } else {
                         idx = int64_t(s ^ ST(xmask));
