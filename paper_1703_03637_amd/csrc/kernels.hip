@@ -1809,11 +1809,14 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     // buffer that is not also an input
     if (P->n_pass > 1 && (!L.u || L.y)) return 1;
     // the pattern table of a pass lives in LDS: at most kMaxPassOps operators,
-    // and with the row tiles (for rows of at most 128 bytes) within 160 KB
+    // and with the row tiles (for rows of at most 128 bytes) and the kernel's
+    // static block-sum array within the 160 KB of a workgroup
     const size_t tile_lds = tile_in_lds(row_bytes, 1) ? size_t(kWavesPerBlock) * 64 * row_bytes : 0;
+    constexpr size_t static_lds = size_t(kWavesPerBlock) * kNQ * 64 * sizeof(double);
     for (int p = 0; p < P->n_pass; ++p) {
         const int n = P->kop_begin[p + 1] - P->kop_begin[p];
-        if (n > kMaxPassOps || size_t(n) * 4 * (CCOEF ? 4 : 2) * sizeof(double) + tile_lds > 160 * 1024) return 1;
+        const size_t table = size_t(n) * 4 * (CCOEF ? 4 : 2) * sizeof(double);
+        if (n > kMaxPassOps || table + tile_lds + static_lds > 160 * 1024) return 1;
     }
     bool staged = sc.windowed == 2 && P->n_pass > 1;
     void* stage[2] = {nullptr, nullptr};

@@ -546,6 +546,33 @@ def test_hv_windowed_tile_partners(monkeypatch, lpr, n_sites, windowed, passes, 
         assert abs(red[1, k] - want) <= 10 * tol * np.linalg.norm(vin[:, k]) * np.linalg.norm(hx[:, k]), k
 
 
+@pytest.mark.parametrize("dt,nvec", [(torch.complex64, 16), (torch.complex128, 8)])
+def test_hv_windowed_pass_too_large_for_lds_falls_back(monkeypatch, dt, nvec):
+    """990 operators with complex elements in one windowed pass: the pattern table (127 KB), the row
+    tiles of 128-byte rows (32 KB) and the kernel's block sums exceed a workgroup's LDS, so the
+    product takes the single-pass kernel instead, with the same result."""
+    print(f"[gpu] windowed pass over the LDS limit dt={dt} nvec={nvec}", flush=True)
+    monkeypatch.setenv("HPHI_WINDOWED", "1")
+    monkeypatch.setenv("HPHI_PASSES", "1")
+    monkeypatch.setenv("HPHI_L2_WINDOW_KB", "65536")
+    monkeypatch.setenv("HPHI_LPR", "4")
+    desc = BasisDesc("spin", 12)
+    rng = np.random.default_rng(17)
+    terms = [L.Term(L.SPIN_FIELD, k % 12, -1, tuple(float(x) for x in rng.uniform(-0.05, 0.05, 3))) for k in range(980)]
+    terms += [L.heisenberg_bond(i, (i + 1) % 12, 1.0) for i in range(10)]
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    assert ham.is_complex
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(400, 400 + nvec)), True)
+    vd = _to_dev(v, dt)
+    u = hp.hphi_hv(ham, vd).cpu().numpy().astype(np.complex128)
+    vin = vd.cpu().numpy().astype(np.complex128)
+    ref = oh.sparse_h(desc, terms, st) @ vin
+    tol = 1e-12 if dt == torch.complex128 else 3e-6
+    assert np.linalg.norm(u - ref) <= tol * np.linalg.norm(ref)
+
+
 # ------------------------------------------------------- batched Lanczos
 
 def _tri12_sectors(dtype, n_iter, use_graph=True, seeds0=500):
