@@ -8,6 +8,7 @@ equations, and brute force on tiny inputs.
 
 import json
 import os
+import math
 from math import comb
 
 import numpy as np
@@ -530,3 +531,90 @@ def test_c_oracle_counted_rank_matches_list_rank(desc, terms):
     assert np.array_equal(c_oracle.unrank_counted(desc, np.arange(len(st))), st)
     ref = oh.sparse_h(desc, terms) @ v
     assert np.allclose(b, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+# ------------------------------------------------- TPQ temperature, variance, c64 rows
+
+def _field_terms(n, h):
+    return [L.Term(L.SPIN_FIELD, i, i, (0.0, 0.0, h)) for i in range(n)]
+
+
+def _free_spin_energy(beta, h):
+    """Canonical energy per site of free spins 1/2 in a field, H = h sum S^z: -(h/2) tanh(beta h/2)."""
+    return -(h / 2.0) * np.tanh(beta * h / 2.0)
+
+
+def test_tpq_beta_free_spins_match_canonical_ensemble():
+    """Sec. 3.5: the mTPQ temperature beta_k = (2k/N_s)/(l - u_k).  For free spins in a field the
+    canonical energy per site is -(h/2) tanh(beta h/2) in closed form; the literal TPQ energy u_k at
+    the oracle's beta_k must match it up to the finite-size and sampling error, while a beta off by a
+    factor of two misses by far more."""
+    ns, h, l = 12, 1.0, 1.0
+    desc = BasisDesc("spin", ns)
+    H = oh.sparse_h(desc, _field_terms(ns, h))
+    psi0 = gaussian_vectors(2 ** ns, [31], True)[:, 0]
+    u, _, _ = osv.tpq(lambda x: H @ x, psi0, ns, l, 81)
+    beta = osv.tpq_beta(u, ns, l)
+    k = np.arange(1, 81)
+    can = _free_spin_energy(beta[k], h)
+    # absolute error on the energy scale h/2 = 0.5: finite size (about 0.01 for the exact ensemble
+    # average at N_s = 12) plus the sampling error of one state of dimension 4096
+    assert np.max(np.abs(u[k] - can)) < 0.04
+    for wrong in (2.0, 0.5):
+        bad = _free_spin_energy(wrong * beta[k], h)
+        assert np.max(np.abs(u[k] - bad)) > 0.1
+    # many spins: the ensemble-averaged mTPQ energy (closed form over the binomial spectrum,
+    # weights (l - E/N)^(2k)) approaches the canonical energy at beta_k to O(1/N)
+    n = 400
+    m = np.arange(n + 1)
+    E = h * (m - n / 2.0)
+    logdeg = np.array([math.lgamma(n + 1) - math.lgamma(x + 1) - math.lgamma(n - x + 1) for x in m])
+    for kk in (1, 10, 100, 400):
+        lw = 2 * kk * np.log(l - E / n) + logdeg
+        w = np.exp(lw - lw.max())
+        uk = float((w * E).sum() / w.sum()) / n
+        b = osv.tpq_beta(np.r_[np.zeros(kk), uk], n, l)[kk]
+        assert abs(uk - _free_spin_energy(b, h)) <= 2e-3 * abs(uk)
+
+
+def test_rayleigh_check_variance_and_residual():
+    """App. A.3: the energy/variance check.  An exact eigenvector has zero variance and residual; an
+    equal superposition of eigenvectors a and b has E = (E_a + E_b)/2, variance ((E_a - E_b)/2)^2 and
+    residual |E_a - E_b|/2."""
+    n = 6
+    terms = L.random_spin_terms(n, 9, 61, conserve_sz=False, fields=True, real=False)
+    Hd = oh.dense_h(BasisDesc("spin", n), terms)
+    evals, evecs = np.linalg.eigh(Hd)
+    apply = lambda x: Hd @ x
+    for a in (0, 5, 40):
+        e, var, res = osv.rayleigh_check(apply, evecs[:, a] * (0.3 - 1.1j))
+        assert abs(e - evals[a]) < 1e-12 and abs(var) < 1e-12 and res < 1e-12
+    for a, b in ((0, 1), (3, 50), (0, 63)):
+        x = (evecs[:, a] * np.exp(0.7j) + evecs[:, b] * np.exp(-1.9j)) * 2.5
+        e, var, res = osv.rayleigh_check(apply, x)
+        half = (evals[a] - evals[b]) / 2
+        assert abs(e - (evals[a] + evals[b]) / 2) < 1e-12
+        assert abs(var - half * half) < 1e-11 * max(1.0, half * half)
+        assert abs(res - abs(half)) < 1e-11
+
+
+@pytest.mark.parametrize("sector", [False, True])
+def test_c_oracle_c64_rows_equal_upcast_rows(sector):
+    """The complex64-input C oracle reads each value, converts it exactly to complex128 and then does
+    the same arithmetic as the complex128 rows, which are pinned against Kronecker and Jordan-Wigner
+    matrices above: on the upcast input the two must agree bit for bit."""
+    from oracle import c_oracle
+    if sector:
+        desc = BasisDesc("fermion", 5, "nupndn", n_up=2, n_dn=3)
+        terms = L.random_fermion_terms(5, 12, 71, conserve_spin=True, real=False, n_dens=3, with_mu=True)
+        st = ob.states(desc)
+        rows, states = st, st
+    else:
+        terms = L.random_spin_terms(9, 14, 72, conserve_sz=False, fields=True, real=False)
+        rows, states = np.arange(2 ** 9, dtype=np.uint64), None
+    dim = len(rows)
+    v = uniform_vectors(dim, [8, 9, 10, 11], True).astype(np.complex64)
+    a = c_oracle.rows_hv(terms, rows, v, states=states)
+    b = c_oracle.rows_hv(terms, rows, v.astype(np.complex128), states=states)
+    assert np.array_equal(a, b)
+    assert np.abs(a).max() > 0
