@@ -57,6 +57,7 @@ enum {
     HPHI_EDEVICE = -3,      /* HIP runtime error (message in hphi_last_error)      */
     HPHI_ESECTOR = -4,      /* a term maps a sector state outside the sector       */
     HPHI_EDTYPE = -5,       /* complex matrix elements with a real storage type    */
+    HPHI_ENONFINITE = -6,   /* a reduction of the run was NaN or Inf (hphi_lanczos) */
     HPHI_INFO_BREAKDOWN = 1, /* Lanczos stopped early: beta below tolerance or dim */
     HPHI_INFO_MAXITER = 2    /* a CG solve reached its iteration limit             */
 };
@@ -160,6 +161,21 @@ int hphi_ham_build(const hphi_basis* basis, const hphi_term* terms, int64_t n_te
 /* 1 if any matrix element is complex (then only C128/C64 storage is allowed). */
 int hphi_ham_is_complex(const hphi_ham* ham, int32_t* is_complex);
 
+/* Non-finite flag word of a Hamiltonian (fault detection for the fused
+ * reductions of Sec. 3.4 and 3.5).  Every reduction the library computes for
+ * calls on this ham -- the four sums of hphi_hv, hphi_tpq_step and
+ * hphi_expect, and the norms of the Lanczos recurrence -- ORs a bit into a
+ * sticky device word when its result is NaN or Inf (a non-finite input
+ * entry, or overflow):
+ *   HPHI_NONFINITE_PRODUCT  a sum of a product call (<x|x>, <x|Hx>, |Hx|^2, |u|^2)
+ *   HPHI_NONFINITE_NORM     a norm of a Lanczos vector (start vector or update)
+ * Products without reductions (opts->reduce == NULL) set nothing.  Writes the
+ * word to *flags (host) and, if clear != 0, resets it to zero.  Synchronizes
+ * `stream`.  hphi_lanczos clears the words of its hams when it starts and
+ * returns HPHI_ENONFINITE if one is set when it ends. */
+enum { HPHI_NONFINITE_PRODUCT = 1, HPHI_NONFINITE_NORM = 2 };
+int hphi_ham_nonfinite(const hphi_ham* ham, int32_t* flags, int32_t clear, void* stream);
+
 void hphi_ham_free(hphi_ham* ham);
 
 /* ------------------------------------------------------------------ H . v */
@@ -249,17 +265,26 @@ int hphi_hv_cma(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32
  * hphi_hv_cma. */
 int hphi_hv_cma_plan(const hphi_ham* ham, int32_t cluster_bits, int32_t* n_clusters, int32_t* sites);
 
-/* Element export from the same device code that hphi_hv uses (parity checks).
- * For rows row0 .. row0+nrows-1, writes up to `cap` elements per row:
+/* Element export through the product kernels themselves (parity checks of
+ * the Sec. 3.3 decode: bit test, XOR target, parity sign, split-table rank).
+ * The product that hphi_hv runs for `nvec` vectors of storage type `dtype`
+ * (C128 or C64: the export follows the complex lane layouts) -- the same
+ * kernel, schedule and operator records -- runs in an export mode: in place
+ * of each gather it records the target index it decoded (for partners that
+ * the windowed kernel takes from its LDS row tile or from another lane, the
+ * partner's configuration as it arrives through that on-chip path) and the
+ * signed element.  For rows row0 .. row0+nrows-1 (at most 2^22 per call)
+ * it then writes up to `cap` elements per row:
  *   the diagonal (col = row, term_id = -1, value = sum of diagonal parts) if nonzero,
- *   then one entry per packed off-diagonal operator whose element is nonzero
- *   (col = target index, term_id = index into the term list, value = signed
- *   matrix element <row|H|col>).
+ *   then one entry per packed off-diagonal operator whose element is nonzero,
+ *   in the order of the operators (col = target index, term_id = index into
+ *   the term list, value = signed matrix element <row|H|col>).
  * cols/re/im/term_id: device [nrows * cap]; counts: device [nrows], the full
- * element count of each row (may exceed cap; extra elements are dropped). */
-int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap,
-                     int64_t* cols, double* re, double* im, int32_t* term_id, int32_t* counts,
-                     void* stream);
+ * element count of each row (may exceed cap; extra elements are dropped).
+ * Allocates a record buffer of nrows * (24 * n_operators + 64) bytes for the
+ * call and synchronizes `stream`. */
+int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap, int64_t nvec, int32_t dtype,
+                     int64_t* cols, double* re, double* im, int32_t* term_id, int32_t* counts, void* stream);
 
 /* ---------------------------------------------------------------- Lanczos */
 
@@ -301,8 +326,14 @@ typedef struct {
  *   hams[n_hams]  one Hamiltonian per independent problem (e.g. Sz sectors)
  *   v0[h]         device start vector, storage dtype, dim_h entries
  *   work[h]       device scratch of 2 * dim_h storage elements
- *   x_out[h]      device FP64 (C128 for complex dtypes) [dim_h], required if refine
+ *   x_out[h]      device FP64 (C128 for complex dtypes) [dim_h], required if refine.
+ *                 It may be the buffer of v0[h] when that buffer holds dim_h
+ *                 FP64 (C128) elements: the second pass copies v0 before x is
+ *                 accumulated, so v0 is then overwritten by the eigenvector
+ *                 (this saves one vector of memory on the largest spaces)
  *   res[h]        results; alpha/beta arrays of n_iter entries each
+ * A non-finite norm or sum anywhere in the recurrence (NaN or Inf in v0, or
+ * overflow) returns HPHI_ENONFINITE after the run (see hphi_ham_nonfinite).
  * Synchronizes `stream` before returning. */
 int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const hphi_lanczos_opts* opts,
                  const void* const* v0, void* const* work, void* const* x_out,
@@ -372,6 +403,24 @@ int hphi_expect(const hphi_ham* obs, const void* psi, int64_t nvec, int32_t dtyp
 int hphi_tpq_step(const hphi_ham* ham, const void* psi_in, void* psi_out, int64_t nvec,
                   int32_t dtype, double l, int32_t k, const double* in_scale, double* obs,
                   void* stream);
+
+/* n_steps consecutive mTPQ steps (Sec. 3.5) of nvec samples, the states
+ * alternating between two caller-owned device buffers: step j = 0 .. n_steps-1
+ * is hphi_tpq_step with k = k0 + j reading psi_a (j even) or psi_b (j odd) and
+ * writing the other, with input scale in_scale (device [nvec] or NULL = 1)
+ * for j = 0 and the previous step's 1/|phi| after that.  The step index and
+ * the scales stay on the device, so with use_graph the steps after the first
+ * are replayed in pairs from one captured HIP graph (no host work per step).
+ *   obs_log  device FP64 [n_steps][4][nvec]: entry [j][q][b] is obs[q*nvec+b]
+ *            of step j as hphi_tpq_step defines it (u, <H^2>/N_s^2, beta of
+ *            the step's input state; 1/|phi| of its output)
+ * The state psi_{k0+n_steps-1} ends in psi_a if n_steps is even, else in
+ * psi_b, unnormalized: its normalizing scale is obs_log[n_steps-1][3][.].
+ * k0 >= 1; n_steps = 0 does nothing.  Allocates a small device state for
+ * the run and synchronizes `stream` before returning. */
+int hphi_tpq_run(const hphi_ham* ham, void* psi_a, void* psi_b, int64_t nvec, int32_t dtype, double l,
+                 int32_t k0, int32_t n_steps, const double* in_scale, double* obs_log, int32_t use_graph,
+                 void* stream);
 
 /* ------------------------------------------------------------------ misc */
 

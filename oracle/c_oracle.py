@@ -39,6 +39,11 @@ def lib():
         L.oracle_hv_rows_counted.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                              C.c_int, C.c_void_p]
         L.oracle_hv_rows_counted.restype = C.c_int
+        L.oracle_hv_rows_counted_ondemand.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int64,
+                                                       C.c_uint64, C.c_int, C.c_void_p]
+        L.oracle_hv_rows_counted_ondemand.restype = C.c_int
+        L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        L.oracle_splitmix64.restype = C.c_uint64
         L.oracle_unrank_counted.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.oracle_unrank_counted.restype = C.c_int
         L.oracle_max_threads.restype = C.c_int
@@ -125,3 +130,18 @@ def unrank_counted(desc, idx: np.ndarray) -> np.ndarray:
     if lib().oracle_unrank_counted(C.byref(sec), idx.ctypes.data, len(idx), cfg.ctypes.data) != 0:
         raise ValueError("rank out of range")
     return cfg
+
+
+def rows_hv_counted_ondemand(desc, terms, rows: np.ndarray, seed: int, nvec: int = 1) -> np.ndarray:
+    """u for the given rows of desc's sector with a real input vector that is never stored:
+    v[t, b] = splitmix_uniform(seed, t * nvec + b) is evaluated per target (real terms only).
+    For sectors too large for host memory (the 36-site kagome Sz = 0 space)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    u = np.zeros((len(rows), nvec), dtype=np.float64)
+    sec = _sector(desc)
+    arr = _terms(terms)
+    rc = lib().oracle_hv_rows_counted_ondemand(arr, len(terms), C.byref(sec), rows.ctypes.data, len(rows),
+                                               C.c_uint64(seed), nvec, u.ctypes.data)
+    if rc != 0:
+        raise ValueError("a term leaves the basis")
+    return u if nvec > 1 else u[:, 0]

@@ -271,6 +271,48 @@ int oracle_hv_rows_counted(const oterm* terms, int nterms, const osector* sec, c
     return bad ? -1 : 0;
 }
 
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a counter-based stream,
+ * element `index` of the stream started at `seed`, mapped to [-1, 1) with
+ * 53 random bits.  Used where an input vector is too large for host memory:
+ * v[t][b] is evaluated on demand from (seed, t * nvec + b). */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t index) {
+    uint64_t z = seed + (index + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double splitmix_uniform(uint64_t seed, uint64_t index) {
+    return (double)(oracle_splitmix64(seed, index) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+/* as oracle_hv_rows_counted, for a real vector v[t*nvec + b] that is not
+ * stored but evaluated on demand (splitmix_uniform(seed, t*nvec + b));
+ * u is real */
+int oracle_hv_rows_counted_ondemand(const oterm* terms, int nterms, const osector* sec, const uint64_t* rows,
+                                    int64_t nrows, uint64_t seed, int nvec, double* u) {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t r = 0; r < nrows; ++r) {
+        branch br[16];
+        double acc[64];
+        for (int b = 0; b < nvec; ++b) acc[b] = 0;
+        for (int k = 0; k < nterms; ++k) {
+            const int n = merge_branches(br, term_apply(&terms[k], rows[r], br));
+            for (int q = 0; q < n; ++q) {
+                if (br[q].c == 0) continue;
+                const int64_t t = rank_count(br[q].s, sec);
+                if (t < 0) { bad = 1; continue; }
+                const double cr = creal(br[q].c);
+                for (int b = 0; b < nvec; ++b)
+                    acc[b] += cr * splitmix_uniform(seed, (uint64_t)t * (uint64_t)nvec + (uint64_t)b);
+            }
+        }
+        for (int b = 0; b < nvec; ++b) u[r * nvec + b] = acc[b];
+    }
+    return bad ? -1 : 0;
+}
+
 /* the configuration of each rank (inverse of rank_count, greedy from the top bit) */
 int oracle_unrank_counted(const osector* sec, const int64_t* idx, int64_t n, uint64_t* cfg) {
     for (int64_t k = 0; k < n; ++k) {

@@ -147,3 +147,16 @@ def tpq_spectral(evals: np.ndarray, evecs: np.ndarray, psi0: np.ndarray, n_sites
         u.append(float((w * evals).sum() / w.sum()) / n_sites)
         h2.append(float((w * evals ** 2).sum() / w.sum()) / n_sites ** 2)
     return np.array(u), np.array(h2)
+
+
+def lowest_eigenvalue(hmat, tol: float = 1e-14) -> float:
+    """Lowest eigenvalue of a sparse Hermitian matrix: ARPACK's implicitly restarted Lanczos
+    (scipy.sparse.linalg.eigsh, smallest algebraic) used as one library step; dense eigh for
+    matrices of dimension <= 64, where ARPACK needs more vectors than the dimension."""
+    import scipy.sparse.linalg as spla
+    n = hmat.shape[0]
+    if n <= 64:
+        return float(np.linalg.eigvalsh(hmat.toarray() if hasattr(hmat, "toarray") else hmat)[0])
+    w = spla.eigsh(hmat, k=1, which="SA", tol=tol, return_eigenvectors=False, ncv=min(n - 1, 40),
+                   v0=np.ones(n, dtype=hmat.dtype) / np.sqrt(n))
+    return float(w[0])

@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     hphi_cg_refine,
     hphi_expect,
     hphi_ham_build,
+    hphi_ham_nonfinite,
     hphi_hv,
     hphi_hv_elements,
     hphi_hv_tune,
@@ -22,6 +23,7 @@ from .binding import (  # noqa: F401
     hphi_hv_cma_plan,
     hphi_lanczos,
     hphi_tpq_step,
+    hphi_tpq_run,
     version,
 )
 from ._lib import HphiError, LIB_PATH  # noqa: F401

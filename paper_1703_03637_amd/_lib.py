@@ -19,6 +19,8 @@ HPHI_ENOMEM = -2
 HPHI_EDEVICE = -3
 HPHI_ESECTOR = -4
 HPHI_EDTYPE = -5
+HPHI_ENONFINITE = -6
+HPHI_NONFINITE_PRODUCT, HPHI_NONFINITE_NORM = 1, 2
 HPHI_INFO_BREAKDOWN = 1
 HPHI_INFO_MAXITER = 2
 
@@ -80,6 +82,7 @@ _SIGS = {
     "hphi_basis_free": ([C.c_void_p], None),
     "hphi_ham_build": ([C.c_void_p, C.POINTER(TermC), C.c_int64, C.POINTER(C.c_void_p)], C.c_int),
     "hphi_ham_is_complex": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
+    "hphi_ham_nonfinite": ([C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_void_p], C.c_int),
     "hphi_ham_free": ([C.c_void_p], None),
     "hphi_hv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.POINTER(HvOptsC),
                  C.c_void_p], C.c_int),
@@ -87,13 +90,15 @@ _SIGS = {
     "hphi_hv_cma": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(HvOptsC),
                      C.c_void_p], C.c_int),
     "hphi_hv_cma_plan": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
-    "hphi_hv_elements": ([C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
-                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hphi_hv_elements": ([C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p,
+                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_lanczos": ([C.POINTER(C.c_void_p), C.c_int32, C.POINTER(LanczosOptsC),
                       C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                       C.POINTER(LanczosResultC), C.c_void_p], C.c_int),
     "hphi_tpq_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "hphi_tpq_run": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                      C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "hphi_cg_refine": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(CgOptsC), C.c_void_p,
                         C.POINTER(CgResultC), C.c_void_p], C.c_int),
     "hphi_expect": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),

@@ -146,6 +146,13 @@ def hphi_ham_build(basis: Basis, terms) -> Ham:
     return Ham(out.value, basis, n)
 
 
+def hphi_ham_nonfinite(ham: Ham, clear: bool = False) -> int:
+    """The sticky non-finite flag word of ham's reductions (HPHI_NONFINITE_* bits); synchronizes."""
+    f = C.c_int32(0)
+    check(L.lib().hphi_ham_nonfinite(C.c_void_p(ham.handle), C.byref(f), int(bool(clear)), _stream()))
+    return int(f.value)
+
+
 # ------------------------------------------------------------------ H . v
 
 def _nvec(v: torch.Tensor, dim: int) -> int:
@@ -212,15 +219,18 @@ def hphi_hv_tune(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None) ->
     return dict(zip(keys, list(out)))
 
 
-def hphi_hv_elements(ham: Ham, row0: int, nrows: int, cap: int):
+def hphi_hv_elements(ham: Ham, row0: int, nrows: int, cap: int, *, nvec: int = 1,
+                     dtype: torch.dtype = torch.complex128):
+    """Element lists of rows row0.. through the product kernels that hphi_hv runs for nvec vectors
+    of `dtype` (complex128 or complex64): (cols, re, im, term, counts)."""
     dev = torch.device("cuda")
     cols = torch.empty(nrows * cap, dtype=torch.int64, device=dev)
     re = torch.empty(nrows * cap, dtype=torch.float64, device=dev)
     im = torch.empty(nrows * cap, dtype=torch.float64, device=dev)
     term = torch.empty(nrows * cap, dtype=torch.int32, device=dev)
     counts = torch.empty(nrows, dtype=torch.int32, device=dev)
-    check(L.lib().hphi_hv_elements(C.c_void_p(ham.handle), row0, nrows, cap, _ptr(cols), _ptr(re), _ptr(im),
-                                   _ptr(term), _ptr(counts), _stream()))
+    check(L.lib().hphi_hv_elements(C.c_void_p(ham.handle), row0, nrows, cap, int(nvec), _DTYPE[dtype], _ptr(cols),
+                                   _ptr(re), _ptr(im), _ptr(term), _ptr(counts), _stream()))
     return (cols.view(nrows, cap), re.view(nrows, cap), im.view(nrows, cap), term.view(nrows, cap), counts)
 
 
@@ -299,3 +309,21 @@ def hphi_tpq_step(ham: Ham, psi_in: torch.Tensor, psi_out: torch.Tensor, l: floa
         raise ValueError("obs must be float64 with 4*nvec entries")
     check(L.lib().hphi_tpq_step(C.c_void_p(ham.handle), _ptr(psi_in), _ptr(psi_out), nv, _dtype_code(psi_in),
                                 float(l), int(k), _ptr(in_scale), _ptr(obs), _stream()))
+
+
+def hphi_tpq_run(ham: Ham, psi_a: torch.Tensor, psi_b: torch.Tensor, l: float, k0: int, n_steps: int,
+                 in_scale: Optional[torch.Tensor] = None, obs_log: Optional[torch.Tensor] = None,
+                 use_graph: bool = True) -> torch.Tensor:
+    """n_steps TPQ steps alternating between psi_a and psi_b; returns the observable log
+    (float64 device tensor [n_steps, 4, nvec]).  The final state is in psi_a if n_steps is even."""
+    nv = _nvec(psi_a, ham.dim)
+    if psi_b.shape != psi_a.shape or psi_b.dtype != psi_a.dtype:
+        raise ValueError("psi_b must match psi_a")
+    if obs_log is None:
+        obs_log = torch.empty((max(n_steps, 1), 4, nv), dtype=torch.float64, device=psi_a.device)
+    if obs_log.dtype != torch.float64 or obs_log.numel() < 4 * nv * n_steps or not obs_log.is_contiguous():
+        raise ValueError("obs_log must be contiguous float64 with n_steps*4*nvec entries")
+    check(L.lib().hphi_tpq_run(C.c_void_p(ham.handle), _ptr(psi_a), _ptr(psi_b), nv, _dtype_code(psi_a), float(l),
+                               int(k0), int(n_steps), _ptr(in_scale), _ptr(obs_log), int(bool(use_graph)),
+                               _stream()))
+    return obs_log

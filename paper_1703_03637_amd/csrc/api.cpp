@@ -1,9 +1,13 @@
 // C entry points: argument checks, the Lanczos driver (Sec. 3.4) and the
 // TPQ step (Sec. 3.5) on top of the product kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "hphi_internal.h"
@@ -23,6 +27,66 @@ int set_error(int code, const char* fmt, ...) {
 int check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return HPHI_OK;
     return set_error(e == hipErrorOutOfMemory ? HPHI_ENOMEM : HPHI_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool alloc_fails() {
+    static std::mutex mu;
+    static std::string armed;
+    static long count = 0;
+    const char* e = std::getenv("HPHI_FAIL_ALLOC");
+    std::lock_guard<std::mutex> g(mu);
+    const std::string cur = e ? e : "";
+    if (cur != armed) {
+        armed = cur;
+        count = 0;
+    }
+    const long n = cur.empty() ? 0 : std::strtol(cur.c_str(), nullptr, 10);
+    if (n <= 0) return false;
+    return ++count == n;
+}
+
+int dev_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (alloc_fails()) return set_error(HPHI_ENOMEM, "%s: device allocation of %zu bytes failed (injected)", what, bytes);
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? HPHI_ENOMEM : HPHI_EDEVICE, "%s: device allocation of %zu bytes: %s",
+                         what, bytes, hipGetErrorString(e));
+    }
+    return HPHI_OK;
+}
+
+// Capture `body` (which enqueues work on the stream it is given) once into a
+// graph and replay it `reps` times on a side stream joined to `st`.
+template <typename Body>
+int replay_pairs(hipStream_t st, Body body, int reps) {
+    hipStream_t cs;
+    int rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
+    if (rc) return rc;
+    hipEvent_t ev;
+    (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    (void)hipEventRecord(ev, st);
+    (void)hipStreamWaitEvent(cs, ev, 0);
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (!rc) {
+        const int r = body(cs);
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        rc = r ? r : check_hip(e, "end capture");
+    }
+    if (!rc) rc = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+    for (int k = 0; !rc && k < reps; ++k) rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
+    (void)hipEventRecord(ev, cs);
+    (void)hipStreamWaitEvent(st, ev, 0);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(ev);
+    return rc;
 }
 
 static bool valid_dtype(int dt) { return dt == HPHI_F64 || dt == HPHI_C128 || dt == HPHI_F32 || dt == HPHI_C64; }
@@ -103,15 +167,57 @@ extern "C" int hphi_hv_cma_plan(const hphi_ham* ham, int32_t cluster_bits, int32
     return HPHI_OK;
 }
 
-extern "C" int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap, int64_t* cols,
-                                double* re, double* im, int32_t* term_id, int32_t* counts, void* stream) {
+extern "C" int hphi_hv_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int32_t cap, int64_t nvec,
+                                int32_t dtype, int64_t* cols, double* re, double* im, int32_t* term_id,
+                                int32_t* counts, void* stream) {
     if (!ham) return set_error(HPHI_EINVAL, "hphi_hv_elements: null ham");
-    if (row0 < 0 || nrows < 0 || row0 + nrows > ham->basis->dim)
+    const hphi_basis* B = ham->basis;
+    if (row0 < 0 || nrows < 0 || row0 + nrows > B->dim)
         return set_error(HPHI_EINVAL, "hphi_hv_elements: rows out of range");
+    if (nrows > (int64_t(1) << 22)) return set_error(HPHI_EINVAL, "hphi_hv_elements: at most 2^22 rows per call");
     if (cap < 1 || !cols || !re || !im || !term_id || !counts)
         return set_error(HPHI_EINVAL, "hphi_hv_elements: bad output arrays");
+    if (!valid_nvec(nvec) || (B->nbits > 32 && nvec > 4))
+        return set_error(HPHI_EINVAL, "hphi_hv_elements: nvec not supported by the product for this space");
+    if (dtype != HPHI_C128 && dtype != HPHI_C64)
+        return set_error(HPHI_EINVAL, "hphi_hv_elements: the export follows a complex storage type (C128 or C64)");
     if (nrows == 0) return HPHI_OK;
-    return launch_elements(ham, row0, nrows, cap, cols, re, im, term_id, counts, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    constexpr int kExportPasses = 8;
+    ExportArgs ex;
+    ex.row0 = row0;
+    ex.nrows = nrows;
+    ex.n_slots = int(ham->ops.size());
+    ex.n_pass = kExportPasses;
+    // tiles of the single-pass kernel that hold the rows
+    auto tile_of = [&](int64_t r) -> int64_t {
+        if (B->dev.sector == 0) return r / kTile;
+        const int64_t k = int64_t(std::upper_bound(B->h_row.begin(), B->h_row.end() - 1, r) - B->h_row.begin()) - 1;
+        return B->h_tile[size_t(k)] + (r - B->h_row[size_t(k)]) / kTile;
+    };
+    ex.t0 = tile_of(row0);
+    ex.t1 = tile_of(row0 + nrows - 1) + 1;
+    const size_t nrec = size_t(nrows) * size_t(ex.n_slots > 0 ? ex.n_slots : 1);
+    const size_t bytes = nrec * 24 + size_t(nrows) * kExportPasses * 8;
+    char* mem = nullptr;
+    if (int rc = dev_alloc((void**)&mem, bytes, "hphi_hv_elements: records")) return rc;
+    ex.col = reinterpret_cast<int64_t*>(mem);
+    ex.cr = reinterpret_cast<double*>(mem + nrec * 8);
+    ex.ci = reinterpret_cast<double*>(mem + nrec * 16);
+    ex.diag = reinterpret_cast<double*>(mem + nrec * 24);
+    int rc = launch_fill_zero(mem, int64_t(bytes), st);
+    HvLaunch L{};
+    L.ham = ham;
+    L.a = 1.0;
+    L.b = 0.0;
+    L.nvec = int(nvec);
+    L.dtype = dtype;
+    L.ex = &ex;
+    if (!rc) rc = launch_hv(L, st);
+    if (!rc) rc = launch_elements_compact(ham, ex, cap, cols, re, im, term_id, counts, st);
+    const hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    return rc ? rc : check_hip(e, "hphi_hv_elements sync");
 }
 
 extern "C" int hphi_expect(const hphi_ham* obs, const void* psi, int64_t nvec, int32_t dtype, double* out,
@@ -162,6 +268,54 @@ extern "C" int hphi_tpq_step(const hphi_ham* ham, const void* psi_in, void* psi_
     return launch_tpq_obs(ham->d_red, obs, int(nvec), ns, l, k, st);
 }
 
+extern "C" int hphi_tpq_run(const hphi_ham* ham, void* psi_a, void* psi_b, int64_t nvec, int32_t dtype, double l,
+                            int32_t k0, int32_t n_steps, const double* in_scale, double* obs_log, int32_t use_graph,
+                            void* stream) {
+    if (!ham || !psi_a || !psi_b || !obs_log) return set_error(HPHI_EINVAL, "hphi_tpq_run: null argument");
+    if (psi_a == psi_b) return set_error(HPHI_EINVAL, "hphi_tpq_run: the two state buffers must differ");
+    if (!valid_nvec(nvec)) return set_error(HPHI_EINVAL, "hphi_tpq_run: nvec must be 1, 2, 4, 8 or 16");
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_tpq_run: bad dtype");
+    if (ham->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_tpq_run: complex Hamiltonian with real storage");
+    if (k0 < 1 || n_steps < 0 || !std::isfinite(l))
+        return set_error(HPHI_EINVAL, "hphi_tpq_run: need k0 >= 1, n_steps >= 0 and finite l");
+    if (n_steps == 0) return HPHI_OK;
+    hipStream_t st = (hipStream_t)stream;
+    TpqRunState* S = nullptr;
+    if (int rc = dev_alloc((void**)&S, sizeof(TpqRunState), "hphi_tpq_run: state")) return rc;
+    const double ns = double(ham->n_sites);
+    // step of parity p reads buffer p (a or b) and writes the other; its input
+    // scale is the caller's for the first step, else the previous step's
+    auto step = [&](int parity, bool first, hipStream_t s) {
+        HvLaunch L{};
+        L.ham = ham;
+        L.v = parity ? psi_b : psi_a;
+        L.u = parity ? psi_a : psi_b;
+        L.sx = first ? in_scale : S->scale[parity ^ 1];
+        L.a = -1.0 / ns;
+        L.b = l;
+        L.nvec = int(nvec);
+        L.dtype = dtype;
+        L.reduce_out = ham->d_red;
+        int rc = launch_hv(L, s);
+        return rc ? rc : launch_tpq_obs_run(ham->d_red, S, obs_log, int(nvec), ns, l, s);
+    };
+    int rc = launch_tpq_run_init(S, k0, st);
+    if (!rc) rc = step(0, true, st);      // eager: allocates lazily built plans before any capture
+    int j = 1;
+    if (!rc && use_graph && n_steps - j >= 4) {
+        rc = replay_pairs(st, [&](hipStream_t cs) {
+            int r = step(1, false, cs);
+            return r ? r : step(0, false, cs);
+        }, (n_steps - j) / 2);
+        if (!rc) j += (n_steps - j) / 2 * 2;
+    }
+    for (; !rc && j < n_steps; ++j) rc = step(j & 1, false, st);
+    const hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(S);
+    return rc ? rc : check_hip(e, "hphi_tpq_run sync");
+}
+
 // ---------------------------------------------------------------- Lanczos
 
 namespace {
@@ -181,7 +335,7 @@ constexpr int kStreamGrid = 1024;
 int lz_alloc(LzDev& D, int n) {
     const size_t bytes = 256 + 3 * size_t(n) * 8 + 64 * 8 + size_t(kStreamGrid) * 8 + 1024;
     char* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return set_error(HPHI_ENOMEM, "hphi_lanczos: scalar workspace");
+    if (int rc = dev_alloc((void**)&p, bytes, "hphi_lanczos: scalar workspace")) return rc;
     D.mem = p;
     D.sc = (LzScalars*)p;
     p += 256;
@@ -226,7 +380,7 @@ int lz_iteration(const hphi_ham* H, int dtype, void* X, void* Y, bool first, LzD
     rc = launch_lz_after_hv(D.sc, D.red, D.alpha, acc ? D.evec : nullptr, st);
     if (rc) return rc;
     rc = launch_lanczos_update(Y, X, H->basis->dim, dtype, &D.sc->c2, acc, &D.sc->ecoef, D.spart, grid, D.red, stop,
-                               st);
+                               H->d_flag, st);
     if (rc) return rc;
     return launch_lz_after_update(D.sc, D.red, D.beta, D.alpha, st);
 }
@@ -237,7 +391,11 @@ int lz_run(const hphi_ham* H, int dtype, const void* v0, void* A, void* B, LzDev
     const int64_t dim = H->basis->dim;
     const int64_t scalars = dim * (dtype_complex(dtype) ? 2 : 1);
     const int grid = stream_grid_for(scalars);
-    int rc = launch_copy_norm(v0, A, dim, dtype, D.spart, grid, D.red, st);
+    int rc = launch_copy_norm(v0, A, dim, dtype, D.spart, grid, D.red, H->d_flag, st);
+    if (rc) return rc;
+    // the eigenvector accumulator starts at zero; it may share v0's buffer,
+    // which is not read again after the copy above
+    if (acc) rc = launch_fill_zero(acc, dim * int64_t(dtype_complex(dtype) ? 16 : 8), st);
     if (rc) return rc;
     rc = launch_lz_init(D.sc, D.red, tol, n_max, st);
     if (rc) return rc;
@@ -301,7 +459,7 @@ int lzb_alloc(LzBatch& D, int n, int n_iter) {
     const size_t arr = size_t(n) * n_iter * 8;
     const size_t bytes = sc_b + 3 * arr + size_t(n) * kNQ * 8 + size_t(kStreamGrid) * 8 + 1024;
     char* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return set_error(HPHI_ENOMEM, "hphi_lanczos: batched workspace");
+    if (int rc = dev_alloc((void**)&p, bytes, "hphi_lanczos: batched workspace")) return rc;
     D.mem = p;
     D.sc = (LzScalars*)p;
     p += sc_b;
@@ -362,6 +520,7 @@ int lzb_plans(const hphi_ham* const* H, int n, int dtype, void* const* A, void* 
                     u.acc = acc ? static_cast<double*>(acc[p]) : nullptr;
                     u.ec = &D.sc[p].ecoef;
                     u.stop = &D.sc[p].stop;
+                    u.flag = H[p]->d_flag;
                     ured[p] = D.red + size_t(kNQ) * p;
                 }
             }
@@ -390,7 +549,9 @@ int lzb_run(const hphi_ham* const* H, int n, int dtype, const void* const* v0, v
         const int64_t dim = H[p]->basis->dim;
         const int grid = stream_grid_for(dim * (dtype_complex(dtype) ? 2 : 1));
         double* red = D.red + size_t(kNQ) * p;
-        int rc = launch_copy_norm(v0[p], A[p], dim, dtype, D.spart, grid, red, st);
+        int rc = launch_copy_norm(v0[p], A[p], dim, dtype, D.spart, grid, red, H[p]->d_flag, st);
+        // eigenvector accumulator (may share v0's buffer, not read again)
+        if (!rc && acc) rc = launch_fill_zero(acc[p], dim * int64_t(dtype_complex(dtype) ? 16 : 8), st);
         if (!rc) rc = launch_lz_init(D.sc + p, red, tol, n_max[p], st);
         if (rc) return rc;
         if (n_max[p] > N) N = n_max[p];
@@ -507,8 +668,6 @@ int lanczos_batched(const hphi_ham* const* hams, int n, const hphi_lanczos_opts&
     if (!rc && o.refine) {
         // second pass: replay every recurrence and accumulate x = sum_k e~_k v_k
         rc = check_hip(hipMemcpyAsync(D.evec, evecs.data(), evecs.size() * 8, hipMemcpyHostToDevice, st), "copy evec");
-        for (int h = 0; h < n && !rc; ++h)
-            rc = launch_fill_zero(x_out[h], hams[h]->basis->dim * int64_t(dtype_size(x_dtype)), st);
         if (!rc) rc = lzb_run(hams, n, o.dtype, v0, A.data(), Bv.data(), D, n_done.data(), tol, x_out,
                               o.use_graph != 0, o.n_iter, st);
         for (int h = 0; h < n && !rc; ++h) rc = refine_one(hams[h], x_out[h], x_dtype, D.red, res[h], st);
@@ -517,6 +676,10 @@ int lanczos_batched(const hphi_ham* const* hams, int n, const hphi_lanczos_opts&
     (void)hipFree(D.mem);
     return rc;
 }
+
+int lanczos_each(const hphi_ham* const* hams, int n_hams, const hphi_lanczos_opts& o, double tol,
+                 const void* const* v0, void* const* work, void* const* x_out, hphi_lanczos_result* res,
+                 hipStream_t st);
 
 // all problems can share one launch: same coefficient type, space kind and width
 bool batchable(const hphi_ham* const* hams, int n) {
@@ -548,8 +711,41 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
     }
     const double tol = o.breakdown_tol > 0 ? o.breakdown_tol : 1e-13;
     hipStream_t st = (hipStream_t)stream;
+    for (int h = 0; h < n_hams; ++h)
+        if (int rc = launch_fill_zero(hams[h]->d_flag, sizeof(int32_t), st)) return rc;
+    const int rc_run = batchable(hams, n_hams) ? lanczos_batched(hams, n_hams, o, tol, v0, work, x_out, res, st)
+                                               : lanczos_each(hams, n_hams, o, tol, v0, work, x_out, res, st);
+    // a NaN or Inf start vector also ends the recurrence at once (its norm is
+    // not positive): the flag word names the cause
+    if (rc_run != HPHI_OK && rc_run != HPHI_EINVAL) return rc_run;
+    const std::string msg = hphi_last_error();
+    for (int h = 0; h < n_hams; ++h) {
+        int32_t f = 0;
+        int rc = check_hip(hipMemcpyAsync(&f, hams[h]->d_flag, sizeof(f), hipMemcpyDeviceToHost, st), "copy flag");
+        if (!rc) rc = check_hip(hipStreamSynchronize(st), "lanczos sync");
+        if (rc) return rc;
+        if (f) return set_error(HPHI_ENONFINITE, "hphi_lanczos: non-finite norm or sum in problem %d (flags %d)", h, f);
+    }
+    if (rc_run) set_error(rc_run, "%s", msg.c_str());
+    return rc_run;
+}
+
+extern "C" int hphi_ham_nonfinite(const hphi_ham* ham, int32_t* flags, int32_t clear, void* stream) {
+    if (!ham || !flags) return set_error(HPHI_EINVAL, "hphi_ham_nonfinite: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = check_hip(hipMemcpyAsync(flags, ham->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy flag");
+    if (!rc && clear) rc = launch_fill_zero(ham->d_flag, sizeof(int32_t), st);
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "flag sync");
+    return rc;
+}
+
+namespace {
+
+// one problem after the other (problems that cannot share a launch)
+int lanczos_each(const hphi_ham* const* hams, int n_hams, const hphi_lanczos_opts& o, double tol,
+                 const void* const* v0, void* const* work, void* const* x_out, hphi_lanczos_result* res,
+                 hipStream_t st) {
     const int x_dtype = dtype_complex(o.dtype) ? HPHI_C128 : HPHI_F64;
-    if (batchable(hams, n_hams)) return lanczos_batched(hams, n_hams, o, tol, v0, work, x_out, res, st);
 
     for (int h = 0; h < n_hams; ++h) {
         const hphi_ham* H = hams[h];
@@ -587,7 +783,6 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
         if (o.refine) {
             // second pass: replay the recurrence and accumulate x = sum_k e~_k v_k
             rc = check_hip(hipMemcpyAsync(D.evec, evec.data(), size_t(n) * 8, hipMemcpyHostToDevice, st), "copy evec");
-            if (!rc) rc = launch_fill_zero(x_out[h], dim * int64_t(dtype_size(x_dtype)), st);
             if (!rc) rc = lz_run(H, o.dtype, v0[h], A, Bv, D, n, tol, x_out[h], o.use_graph != 0, st);
             if (rc) return fail(rc);
             rc = refine_one(H, x_out[h], x_dtype, D.red, res[h], st);
@@ -597,6 +792,8 @@ extern "C" int hphi_lanczos(const hphi_ham* const* hams, int32_t n_hams, const h
     }
     return HPHI_OK;
 }
+
+}  // namespace
 
 extern "C" int hphi_cg_refine(const hphi_ham* ham, void* x, int32_t dtype, double e_approx,
                               const hphi_cg_opts* opts, void* work, hphi_cg_result* res, void* stream) {
@@ -617,8 +814,7 @@ extern "C" int hphi_cg_refine(const hphi_ham* ham, void* x, int32_t dtype, doubl
     double* P = R + n;
     double* Q = P + n;
     double* mem = nullptr;
-    if (hipMalloc(&mem, (2048 + 64) * sizeof(double)) != hipSuccess)
-        return set_error(HPHI_ENOMEM, "hphi_cg_refine: workspace");
+    if (int rc0 = dev_alloc((void**)&mem, (2048 + 64) * sizeof(double), "hphi_cg_refine: workspace")) return rc0;
     double* partials = mem;
     double* red = mem + 2048;                // [0..3] product sums, [8] a norm
     const double Ep = e_approx + o.shift;

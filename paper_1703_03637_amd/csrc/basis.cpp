@@ -85,7 +85,7 @@ extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
             return set_error(HPHI_EINVAL, "hphi_basis_build: bad sector %d", d.sector);
     }
 
-    hphi_basis* B = new (std::nothrow) hphi_basis();
+    hphi_basis* B = alloc_fails() ? nullptr : new (std::nothrow) hphi_basis();
     if (!B) return set_error(HPHI_ENOMEM, "hphi_basis_build: host allocation");
     B->desc = d;
     B->nbits = nbits;
@@ -200,9 +200,9 @@ extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
            sz_hb = align256(n_high * 4), sz_lows = align256(n_lo * 4);
     size_t total = sz_jlo + sz_jhi + sz_hv + sz_hr + sz_ht + sz_hb + sz_lows;
     char* base = nullptr;
-    if (hipMalloc(&base, total) != hipSuccess) {
+    if (int rc = dev_alloc((void**)&base, total, "hphi_basis_build: rank tables")) {
         delete B;
-        return set_error(HPHI_ENOMEM, "hphi_basis_build: device allocation of %zu bytes", total);
+        return rc;
     }
     B->dmem = base;
     char* p = base;
@@ -231,6 +231,8 @@ extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
         delete B;
         return check_hip(e, "hphi_basis_build: table upload");
     }
+    B->h_row = std::move(h_row);
+    B->h_tile = std::move(h_tile);
     *out = B;
     return HPHI_OK;
 }

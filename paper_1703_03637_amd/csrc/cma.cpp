@@ -113,9 +113,9 @@ CmaPlan* build_cma_plan(const hphi_ham* H, int M) {
     }
     std::vector<float> hf(hd.size());
     for (size_t i = 0; i < hd.size(); ++i) hf[i] = float(hd[i]);
-    if (hipMalloc(&P->d_hd, hd.size() * sizeof(double)) != hipSuccess ||
-        hipMalloc(&P->d_hf, hf.size() * sizeof(float)) != hipSuccess ||
-        hipMalloc(&P->d_bits, P->bits.size() * sizeof(int32_t)) != hipSuccess) {
+    if (dev_alloc((void**)&P->d_hd, hd.size() * sizeof(double), "dense-block plan") ||
+        dev_alloc((void**)&P->d_hf, hf.size() * sizeof(float), "dense-block plan") ||
+        dev_alloc((void**)&P->d_bits, P->bits.size() * sizeof(int32_t), "dense-block plan")) {
         if (P->d_hd) (void)hipFree(P->d_hd);
         if (P->d_hf) (void)hipFree(P->d_hf);
         delete P;

@@ -73,6 +73,7 @@ struct alignas(128) KOp {
     T ci[4];
     T d[4];
     uint32_t lq;
+    int32_t op;   // index of the operator in the Hamiltonian's list (-1 for padding)
 };
 
 // Pass plan of the windowed full-space product.  Each pass applies the
@@ -146,9 +147,10 @@ struct hphi_basis {
     int device = 0;
     hphi::BasisDev dev{};
     void* dmem = nullptr;
-    // host copies (validation and host-side rank checks)
+    // host copies (validation, host-side rank checks, row -> tile for exports)
     std::vector<uint32_t> j_lo;
     std::vector<int64_t> j_hi;
+    std::vector<int64_t> h_row, h_tile;
 };
 
 struct hphi_ham {
@@ -163,6 +165,7 @@ struct hphi_ham {
     int grid = 0;                 // persistent grid of the product kernels
     double* d_partials = nullptr; // [kMaxGrid][kNQ * kMaxNvec]
     double* d_red = nullptr;      // [kNQ * kMaxNvec]
+    int32_t* d_flag = nullptr;    // sticky non-finite flag word of the reductions (device, one int)
     std::mutex plan_mu;           // guards the lazily built pass plans, staging buffers and tuned schedules
     void* d_stage[2] = {nullptr, nullptr};   // copies of v in a later pass's order (staged schedule)
     size_t stage_bytes[2] = {0, 0};
@@ -181,6 +184,32 @@ namespace hphi {
 int set_error(int code, const char* fmt, ...);
 int check_hip(hipError_t e, const char* what);
 
+// Every device allocation of the library goes through dev_alloc, and the
+// large host structures of the builders check alloc_fails first.  Test hook:
+// if the environment variable HPHI_FAIL_ALLOC holds a number N > 0, the N-th
+// allocation counted from the moment the variable took its current value
+// fails as if memory were exhausted (status HPHI_ENOMEM).
+bool alloc_fails();
+int dev_alloc(void** p, size_t bytes, const char* what);
+
+// Element export through the product kernels (hphi_hv_elements): instead of
+// gathering and accumulating, the kernel records for every row in
+// [row0, row0 + nrows) and every operator slot o < n_slots the target index
+// and the signed element it decoded (col[r][o], cr[r][o], ci[r][o]; rows are
+// relative to row0), and the diagonal sum of its pass in diag[r][pass].
+// Tiles [t0, t1) of the single-pass kernel cover the rows (the windowed
+// kernel visits every tile).
+struct ExportArgs {
+    int64_t row0 = 0, nrows = 0;
+    int64_t t0 = 0, t1 = 0;
+    int n_slots = 0;
+    int n_pass = 1;
+    int64_t* col = nullptr;
+    double* cr = nullptr;
+    double* ci = nullptr;
+    double* diag = nullptr;
+};
+
 // launch wrappers (kernels.hip)
 struct HvLaunch {
     const hphi_ham* ham;
@@ -195,20 +224,22 @@ struct HvLaunch {
     const int* stop;         // device flag: skip all work if nonzero (nullptr = never)
     double* reduce_out;      // device [kNQ * nvec] or nullptr (quantity-major)
     const Schedule* sched;   // nullptr: the tuned or default schedule
+    const ExportArgs* ex;    // non-null: element export instead of the product
 };
 Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype);
 int launch_hv(const HvLaunch& L, hipStream_t st);
-int launch_elements(const hphi_ham* ham, int64_t row0, int64_t nrows, int cap, int64_t* cols,
-                    double* re, double* im, int32_t* term, int32_t* counts, hipStream_t st);
+// compact the records of an export into the element lists of hphi_hv_elements
+int launch_elements_compact(const hphi_ham* ham, const ExportArgs& ex, int cap, int64_t* cols, double* re,
+                            double* im, int32_t* term, int32_t* counts, hipStream_t st);
 int launch_rank(const hphi_basis* b, const uint64_t* cfg, int64_t* idx, int64_t n, hipStream_t st);
 int launch_unrank(const hphi_basis* b, const int64_t* idx, uint64_t* cfg, int64_t n, hipStream_t st);
 
 // Lanczos / TPQ support kernels
 int launch_copy_norm(const void* src, void* dst, int64_t n, int dtype, double* partials, int grid,
-                     double* red, hipStream_t st);
+                     double* red, int32_t* flag, hipStream_t st);
 int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const double* c2,
                           void* acc, const double* ecoef, double* partials, int grid, double* red,
-                          const int* stop, hipStream_t st);
+                          const int* stop, int32_t* flag, hipStream_t st);
 int launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 // w = a x + b y (FP64, n scalars; w may alias x or y); |w|^2 into *norm2 if non-null
 int launch_lincomb(double* w, const double* x, const double* y, int64_t n, double a, double b, double* partials,
@@ -216,6 +247,17 @@ int launch_lincomb(double* w, const double* x, const double* y, int64_t n, doubl
 int launch_expect(const double* red, double* out, int nvec, hipStream_t st);
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k,
                    hipStream_t st);
+// device state of a multi-step TPQ run (hphi_tpq_run): the next step's index
+// k, the step counter j, and the normalizing scales of the last two states
+struct TpqRunState {
+    int32_t k;
+    int32_t j;
+    int32_t pad[2];
+    double scale[2][kMaxNvec];
+};
+int launch_tpq_run_init(TpqRunState* s, int k0, hipStream_t st);
+int launch_tpq_obs_run(const double* red, TpqRunState* s, double* obs_log, int nvec, double n_sites, double l,
+                       hipStream_t st);
 
 // per-iteration scalar bookkeeping of the Lanczos recurrence (device, one thread)
 struct LzScalars {
@@ -241,6 +283,7 @@ struct RedDesc {             // reduce partials[n_parts][nq] into out[nq]
     int pad;
     double* out;
     const int* stop;
+    int32_t* flag;           // non-finite flag word of the problem (or nullptr)
 };
 struct UpdDesc {             // y += c2 x, |y|^2 partials, acc += ec x
     void* y;
@@ -251,6 +294,7 @@ struct UpdDesc {             // y += c2 x, |y|^2 partials, acc += ec x
     const double* ec;
     double* partials;        // set by the plan
     const int* stop;
+    int32_t* flag;           // non-finite flag word of the problem's Hamiltonian
 };
 // Launch plan of one batched product: per-problem arguments, block ranges
 // (multiples of 8) and reductions, uploaded once and replayed by graphs.

@@ -269,6 +269,29 @@ __host__ __device__ constexpr void vec_lane(int g, int& sub, int& bi) {
     bi = ((c / LPR) * Ly::CPS + eg % Ly::CPS) / NC;
 }
 
+// acc += c * g for one gathered row (c = cr + i ci), FP64.  A lane whose
+// element is zero (act false) adds exactly zero: its g registers hold a stale
+// or partner row that may be non-finite, and 0 * Inf would be NaN.
+template <typename S, bool CPLX, bool CCOEF, int VPL>
+__device__ __forceinline__ void accumulate(double (&acc)[VPL * (CPLX ? 2 : 1)], const S (&g)[VPL * (CPLX ? 2 : 1)],
+                                           bool act, double cr, double ci) {
+#pragma unroll
+    for (int b = 0; b < VPL; ++b) {
+        if constexpr (CPLX) {
+            const double gr = double(act ? g[2 * b] : S(0)), gi = double(act ? g[2 * b + 1] : S(0));
+            if constexpr (CCOEF) {
+                acc[2 * b] += cr * gr - ci * gi;
+                acc[2 * b + 1] += cr * gi + ci * gr;
+            } else {
+                acc[2 * b] += cr * gr;
+                acc[2 * b + 1] += cr * gi;
+            }
+        } else {
+            acc[b] += cr * double(act ? g[b] : S(0));
+        }
+    }
+}
+
 struct HvArgs {
     BasisDev bs;
     const DevOp* ops;    // padded to n_ops (a multiple of 4)
@@ -282,6 +305,7 @@ struct HvArgs {
     double a, b;
     const int* stop;
     double* partials;
+    ExportArgs ex;       // element export (EXPORT instantiations only)
 };
 
 // the packed operator table seen through the constant address space
@@ -421,7 +445,10 @@ constexpr size_t kLdsStageBytes = 64 * 1024;
 // W64: configurations above 32 bits, TAB: table placement (0: pattern and
 // low rank tables staged in LDS, 1: both read from global memory, 2: pattern
 // table in LDS, low rank table from global memory).
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
+// EXPORT: the element export of the same decode (no gathers, no output):
+// per row in the export range and operator slot o, the target index and the
+// signed element are recorded; the diagonal sum goes to the row's pass-0 slot.
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB, bool EXPORT = false>
 __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const int nblk) {
     using ST = typename StateT<W64>::type;
     constexpr int NC = CPLX ? 2 : 1;
@@ -486,23 +513,34 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     // XCD-aware tile range: blocks blk, blk + 8, ... share an XCD and sweep
     // its contiguous eighth of the tiles
     const int xcd = blk & 7;
-    const int waves_x = (nblk >> 3) * kWavesPerBlock;
-    const int wl = (blk >> 3) * kWavesPerBlock + wave;
-    const int64_t T = bs.n_tiles;
-    const int64_t Tx = (T + 7) >> 3;
-    const int64_t t_begin = xcd * Tx;
-    const int64_t t_end = (t_begin + Tx < T) ? t_begin + Tx : T;
+    int64_t tile_first, t_end, tile_step;
+    if constexpr (EXPORT) {
+        // the tiles that hold the export's rows, dealt over every wavefront
+        tile_first = A.ex.t0 + int64_t(blk) * kWavesPerBlock + wave;
+        t_end = A.ex.t1;
+        tile_step = int64_t(nblk) * kWavesPerBlock;
+    } else {
+        const int waves_x = (nblk >> 3) * kWavesPerBlock;
+        const int wl = (blk >> 3) * kWavesPerBlock + wave;
+        const int64_t T = bs.n_tiles;
+        const int64_t Tx = (T + 7) >> 3;
+        const int64_t t_begin = xcd * Tx;
+        t_end = (t_begin + Tx < T) ? t_begin + Tx : T;
+        tile_first = t_begin + wl;
+        tile_step = waves_x;
+    }
 
     double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
     // gathered rows stay live across operators: a lane whose element is zero
-    // skips its load and multiplies the previous (finite) values by 0.0
+    // skips its load, and the accumulation takes zero in place of its stale
+    // registers, so a non-finite entry of v reaches only the rows it couples to
     alignas(16) S g[4][NE];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int e = 0; e < NE; ++e) g[k][e] = S(0);
 
-    for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
+    for (int64_t tile = tile_first; tile < t_end; tile += tile_step) {
         int64_t k_hi = 0, tile_row0 = 0, cnt = kTile, hrow = 0;
         ST hbits = 0;
         uint64_t hval = 0;
@@ -594,32 +632,34 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
 #pragma unroll
                     for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(ik[k]));
                 }
+                if constexpr (EXPORT) {
+                    if (valid && sub == 0 && row >= A.ex.row0 && row < A.ex.row0 + A.ex.nrows) {
+                        const size_t rb = size_t(row - A.ex.row0) * size_t(A.ex.n_slots);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
-                    if (act) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double cr = crk[k], ci = cik[k];
-#pragma unroll
-                    for (int b = 0; b < VPL; ++b) {
-                        if constexpr (CPLX) {
-                            const double gr = double(g[k][2 * b]), gi = double(g[k][2 * b + 1]);
-                            if constexpr (CCOEF) {
-                                acc[2 * b] += cr * gr - ci * gi;
-                                acc[2 * b + 1] += cr * gi + ci * gr;
-                            } else {
-                                acc[2 * b] += cr * gr;
-                                acc[2 * b + 1] += cr * gi;
+                        for (int k = 0; k < 4; ++k)
+                            if (o + k < A.ex.n_slots) {
+                                A.ex.col[rb + o + k] = ik[k];
+                                A.ex.cr[rb + o + k] = crk[k];
+                                A.ex.ci[rb + o + k] = cik[k];
                             }
-                        } else {
-                            acc[b] += cr * double(g[k][b]);
-                        }
                     }
+                    continue;
                 }
+                bool actk[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                    if (actk[k]) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL>(acc, g[k], actk[k], crk[k], cik[k]);
             }
 
+            if constexpr (EXPORT) {
+                if (valid && sub == 0 && row >= A.ex.row0 && row < A.ex.row0 + A.ex.nrows)
+                    A.ex.diag[size_t(row - A.ex.row0) * size_t(A.ex.n_pass)] = dsum;
+                continue;
+            }
             // epilogue: u = a * H x + b * x + cy * y with x = sx * v
             double xr[NE], ur[NE];
             if (valid) {
@@ -666,6 +706,7 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
             wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
         }
     }
+    if constexpr (EXPORT) return;
 
     __shared__ double sh[kWavesPerBlock][kNQ][64];
 #pragma unroll
@@ -683,9 +724,9 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     }
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB, bool EXPORT>
 __global__ __launch_bounds__(kBlock) void hv_kernel(HvArgs A) {
-    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>(A, int(blockIdx.x), int(gridDim.x));
+    hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EXPORT>(A, int(blockIdx.x), int(gridDim.x));
 }
 
 // Several problems in one launch (uneven sector sizes): problem p owns the
@@ -739,9 +780,33 @@ struct HvwArgs {
     double a, b;
     const int* stop;
     double* partials;
+    int pass;            // index of this pass (element export)
+    ExportArgs ex;
 };
 
-template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT>
+// Payload of the element export: the row's configuration in the first four
+// bytes of a lane's share, so the on-chip partner paths (LDS tile, lane
+// exchange) move configurations instead of values.
+template <typename S, int NE>
+__device__ __forceinline__ void export_payload(uint32_t s, S (&x)[NE]) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) x[e] = S(0);
+    __builtin_memcpy(&x[0], &s, 4);
+}
+
+template <typename S, int NE>
+__device__ __forceinline__ uint32_t export_config(const S (&x)[NE]) {
+    uint32_t s;
+    __builtin_memcpy(&s, &x[0], 4);
+    return s;
+}
+
+// EXPORT: the element export of this pass's decode (no memory gathers and no
+// output): records the target configuration of every operator of the pass --
+// for partners inside the tile the configuration travels through the same LDS
+// tile or lane exchange that carries values in the product -- its signed
+// element, and the pass's diagonal sum.
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT, bool EXPORT = false>
 __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     constexpr int NC = CPLX ? 2 : 1;
     constexpr int VPL = B / LPR;
@@ -815,7 +880,8 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     char* tb = reinterpret_cast<char*>(lds_dyn) + size_t(n_ops) * 4 * TE * sizeof(double) + size_t(wave) * 64 * TRB;
 
     // gathered rows stay live across operators: a lane whose element is zero
-    // skips its load and multiplies the previous (finite) values by 0.0
+    // skips its load, and the accumulation takes zero in place of its stale
+    // or partner registers (non-finite entries stay with the rows they couple to)
     alignas(16) S g[4][NE];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -843,7 +909,8 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 for (int k = 0; k < 6; ++k)
                     if ((r >> k) & 1) s |= 1u << perm[k];
                 const uint32_t base = gq ? ((uint32_t(tile) << 6) | uint32_t(r)) : s;
-                load_lane<S, NE, LPR>(v, int64_t(base), sub, tv[pass]);
+                if constexpr (EXPORT) export_payload<S, NE>(s, tv[pass]);
+                else load_lane<S, NE, LPR>(v, int64_t(base), sub, tv[pass]);
             }
 #pragma unroll
             for (int pass = 0; pass < LPR; ++pass) tile_put<S, NE, LPR>(tb, pass * RPW + rlane, sub, tv[pass]);
@@ -870,7 +937,9 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             // exchanged from them between lanes)
             alignas(16) S vr[NE];
             if constexpr (TL) tile_get<S, NE, LPR>(tb, r, sub, vr);
+            else if constexpr (EXPORT) export_payload<S, NE>(s, vr);
             else load_lane<S, NE, LPR>(v, int64_t(base), sub, vr);
+            const bool ex_row = EXPORT && sub == 0 && int64_t(s) >= A.ex.row0 && int64_t(s) < A.ex.row0 + A.ex.nrows;
             double acc[NE];
 #pragma unroll
             for (int e = 0; e < NE; ++e) acc[e] = 0.0;
@@ -882,10 +951,12 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 uint32_t tk[4];
                 bool lk[4];   // partner on chip: in the LDS tile, or in this wavefront pass (uniform)
                 int xa[4];
+                int opk[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const ConstKOp& rec = kops[A.kop_begin + o + k];
                     const uint32_t xm = rec.xm, sm = rec.sm, bi = rec.bi, bj = rec.bj, lq = rec.lq;
+                    opk[k] = EXPORT ? rec.op : -1;
                     lk[k] = (lq >> LOGT) == 0u;
                     // partner: tile row r ^ lq, or the byte address of its lane
                     xa[k] = TL ? int(lq & 63u) : (lane ^ int(lq << LOGL)) << 2;
@@ -907,36 +978,49 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                     cik[k] = ci;
                     tk[k] = base ^ xm;
                 }
+                if constexpr (EXPORT) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        uint32_t t = tk[k];
+                        if (lk[k]) {
+                            // the partner row's payload through the on-chip path
+                            if constexpr (TL) tile_get<S, NE, LPR>(tb, r ^ int(xa[k]), sub, g[k]);
+                            else exchange_lane<S, NE>(vr, xa[k], g[k]);
+                            t = export_config<S, NE>(g[k]);
+                        } else if (gq) {
+                            // staged copy: tk is the partner's processing index
+                            uint32_t c = 0;
+                            for (int b = 0; b < A.nbits; ++b)
+                                if ((t >> b) & 1u) c |= 1u << perm[b];
+                            t = c;
+                        }
+                        if (ex_row && opk[k] >= 0) {
+                            const size_t at = size_t(int64_t(s) - A.ex.row0) * size_t(A.ex.n_slots) + size_t(opk[k]);
+                            A.ex.col[at] = int64_t(t);
+                            A.ex.cr[at] = crk[k];
+                            A.ex.ci[at] = cik[k];
+                        }
+                    }
+                    continue;
+                }
+                bool actk[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const bool act = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                    actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
                     if (lk[k]) {
                         if constexpr (TL) tile_get<S, NE, LPR>(tb, r ^ int(xa[k]), sub, g[k]);
                         else exchange_lane<S, NE>(vr, xa[k], g[k]);
                     }
-                    else if (act) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
+                    else if (actk[k]) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double cr = crk[k], ci = cik[k];
-#pragma unroll
-                    for (int b = 0; b < VPL; ++b) {
-                        if constexpr (CPLX) {
-                            const double gr = double(g[k][2 * b]), gi = double(g[k][2 * b + 1]);
-                            if constexpr (CCOEF) {
-                                acc[2 * b] += cr * gr - ci * gi;
-                                acc[2 * b + 1] += cr * gi + ci * gr;
-                            } else {
-                                acc[2 * b] += cr * gr;
-                                acc[2 * b + 1] += cr * gi;
-                            }
-                        } else {
-                            acc[b] += cr * double(g[k][b]);
-                        }
-                    }
-                }
+                for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL>(acc, g[k], actk[k], crk[k], cik[k]);
             }
 
+            if constexpr (EXPORT) {
+                if (ex_row) A.ex.diag[size_t(int64_t(s) - A.ex.row0) * size_t(A.ex.n_pass) + size_t(A.pass)] = dsum;
+                continue;
+            }
             if (stg) {
                 if constexpr (NT) store_lane_nt<S, NE, LPR>(stg, int64_t(qn), sub, vr);
                 else store_lane<S, NE, LPR>(stg, int64_t(qn), sub, vr);
@@ -996,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             wave_reduce_quantities<VPL, LPR, NC, NE>(xr, acc, ur, wq, lane);
         }
     }
-    if (!last) return;
+    if (!last || EXPORT) return;
     __shared__ double sh[kWavesPerBlock][kNQ][64];
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) sh[wave][k][lane] = wq[k];
@@ -1283,9 +1367,10 @@ __global__ __launch_bounds__(kBlock) void cma_kernel(CmaArgs A) {
     }
 }
 
-// out[q] = sum over g of partials[g * nq + q], fixed order
+// out[q] = sum over g of partials[g * nq + q], fixed order.  A non-finite
+// sum sets `bit` in the problem's sticky flag word (if given).
 __device__ __forceinline__ void reduce_body(const double* __restrict__ partials, int n_parts, int nq, int q,
-                                            double* __restrict__ out) {
+                                            double* __restrict__ out, int32_t* flag, int32_t bit) {
     double s = 0.0;
     for (int g = threadIdx.x; g < n_parts; g += 256) s += partials[size_t(g) * nq + q];
     __shared__ double sh[256];
@@ -1295,15 +1380,18 @@ __device__ __forceinline__ void reduce_body(const double* __restrict__ partials,
         if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[q] = sh[0];
+    if (threadIdx.x == 0) {
+        out[q] = sh[0];
+        if (flag && !isfinite(sh[0])) atomicOr(flag, bit);
+    }
 }
 
 // one block per quantity q
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partials, int n_parts,
                                                               int nq, double* __restrict__ out,
-                                                              const int* stop) {
+                                                              const int* stop, int32_t* flag, int32_t bit) {
     if (stop && *stop) return;
-    reduce_body(partials, n_parts, nq, int(blockIdx.x), out);
+    reduce_body(partials, n_parts, nq, int(blockIdx.x), out, flag, bit);
 }
 
 // several problems: block p * nq + q reduces quantity q of problem p
@@ -1314,54 +1402,40 @@ __global__ __launch_bounds__(256) void reduce_multi_kernel(const RedDesc* __rest
     double* out = d[p].out;
     const int* stop = d[p].stop;
     if (stop && *stop) return;
-    reduce_body(partials, n_parts, nq, q, out);
+    reduce_body(partials, n_parts, nq, q, out, d[p].flag, nq == 1 ? HPHI_NONFINITE_NORM : HPHI_NONFINITE_PRODUCT);
 }
 
-// ---- element export (same operator evaluation as hv_kernel, FP64 values)
-template <bool SECTOR>
-__global__ __launch_bounds__(256) void elements_kernel(BasisDev bs, const DevOp* __restrict__ ops, int n_ops,
-                                                       int64_t row0, int64_t nrows, int cap,
-                                                       int64_t* __restrict__ cols, double* __restrict__ re,
-                                                       double* __restrict__ im, int32_t* __restrict__ term,
-                                                       int32_t* __restrict__ counts) {
+// ---- element lists from the records of an export: per row the diagonal (sum
+// of the passes' diagonal parts, in pass order) if nonzero, then the nonzero
+// off-diagonal elements in the order of the Hamiltonian's operator list
+__global__ __launch_bounds__(256) void elements_compact_kernel(ExportArgs ex, const DevOp* __restrict__ ops, int cap,
+                                                               int64_t* __restrict__ cols, double* __restrict__ re,
+                                                               double* __restrict__ im, int32_t* __restrict__ term,
+                                                               int32_t* __restrict__ counts) {
     const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (r >= nrows) return;
-    const int64_t row = row0 + r;
-    const uint64_t s = unrank_row(bs, row);
-    int n = 0;
+    if (r >= ex.nrows) return;
     double dsum = 0.0;
-    for (int o = 0; o < n_ops; ++o) {
-        const DevOp& op = ops[o];
-        const int p = int((s >> op.bi) & 1u) | (int((s >> op.bj) & 1u) << 1);
-        dsum += sel4(p, op.d[0], op.d[1], op.d[2], op.d[3]);
-    }
-    const size_t base = size_t(r) * cap;
+    for (int p = 0; p < ex.n_pass; ++p) dsum += ex.diag[size_t(r) * ex.n_pass + p];
+    const size_t out = size_t(r) * cap;
+    int n = 0;
     if (dsum != 0.0) {
         if (n < cap) {
-            cols[base + n] = row;
-            re[base + n] = dsum;
-            im[base + n] = 0.0;
-            term[base + n] = -1;
+            cols[out + n] = ex.row0 + r;
+            re[out + n] = dsum;
+            im[out + n] = 0.0;
+            term[out + n] = -1;
         }
         ++n;
     }
-    for (int o = 0; o < n_ops; ++o) {
-        const DevOp& op = ops[o];
-        if (op.xmask == 0) continue;
-        const int p = int((s >> op.bi) & 1u) | (int((s >> op.bj) & 1u) << 1);
-        double cr = sel4(p, op.cr[0], op.cr[1], op.cr[2], op.cr[3]);
-        double ci = sel4(p, op.ci[0], op.ci[1], op.ci[2], op.ci[3]);
+    const size_t rb = size_t(r) * ex.n_slots;
+    for (int o = 0; o < ex.n_slots; ++o) {
+        const double cr = ex.cr[rb + o], ci = ex.ci[rb + o];
         if (cr == 0.0 && ci == 0.0) continue;
-        const uint64_t t = s ^ op.xmask;
-        if (op.smask != 0 && (__popcll(s & op.smask) & 1)) {
-            cr = -cr;
-            ci = -ci;
-        }
         if (n < cap) {
-            cols[base + n] = rank_of<SECTOR>(bs, t);
-            re[base + n] = cr;
-            im[base + n] = ci;
-            term[base + n] = op.term;
+            cols[out + n] = ex.col[rb + o];
+            re[out + n] = cr;
+            im[out + n] = ci;
+            term[out + n] = ops[o].term;
         }
         ++n;
     }
@@ -1514,6 +1588,39 @@ __global__ void tpq_obs_kernel(const double* __restrict__ red, double* __restric
     obs[3 * nvec + b] = 1.0 / sqrt(uu);
 }
 
+// TPQ observables of a step inside a run: the step number lives on the
+// device (graph replays advance it); the scale of the produced state goes
+// to the slot of this step's parity, where the next step reads it.
+__global__ void tpq_obs_run_kernel(const double* __restrict__ red, TpqRunState* st, double* __restrict__ obs_log,
+                                   int nvec, double ns, double l) {
+    const int b = threadIdx.x;
+    const int j = st->j;
+    if (b < nvec) {
+        const double xx = red[0 * nvec + b], xh = red[1 * nvec + b], hh = red[2 * nvec + b],
+                     uu = red[3 * nvec + b];
+        const double uk = xh / xx / ns;
+        double* o = obs_log + size_t(j) * 4 * nvec;
+        o[0 * nvec + b] = uk;
+        o[1 * nvec + b] = hh / xx / (ns * ns);
+        o[2 * nvec + b] = (2.0 * double(st->k - 1) / ns) / (l - uk);
+        const double s = 1.0 / sqrt(uu);
+        o[3 * nvec + b] = s;
+        st->scale[j & 1][b] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->j = j + 1;
+        st->k = st->k + 1;
+    }
+}
+
+__global__ void tpq_run_init_kernel(TpqRunState* st, int k0) {
+    if (threadIdx.x == 0) {
+        st->k = k0;
+        st->j = 0;
+    }
+}
+
 __global__ void lz_init_kernel(LzScalars* sc, const double* red, double tol, int n_max) {
     const double nn = red[0];
     sc->s_cur = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
@@ -1638,11 +1745,12 @@ static int occupancy_with_lds(int occ, size_t lds) {
     return by_lds < occ ? (by_lds < 1 ? 1 : by_lds) : occ;
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, int TAB, bool EX>
 static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStream_t st) {
     const hphi_ham* H = L.ham;
-    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>);
-    const int grid = make_grid(occupancy_with_lds(occ, lds), sc, H->basis->dev.n_tiles);
+    static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EX>);
+    const int64_t tiles = EX ? L.ex->t1 - L.ex->t0 : H->basis->dev.n_tiles;
+    const int grid = make_grid(occupancy_with_lds(occ, lds), sc, tiles < 1 ? 1 : tiles);
     HvArgs A;
     A.bs = H->basis->dev;
     A.ops = H->d_ops;
@@ -1657,11 +1765,13 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
-    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB><<<grid, kBlock, lds, st>>>(A);
+    if constexpr (EX) A.ex = *L.ex;
+    hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EX><<<grid, kBlock, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
-    if (L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop);
+    if (!EX && L.reduce_out) {
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop, H->d_flag,
+                                                      HPHI_NONFINITE_PRODUCT);
         rc = check_hip(hipGetLastError(), "reduce launch");
     }
     return rc;
@@ -1670,66 +1780,66 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
 // Table placement: 0 = pattern table and low rank table in LDS, 1 = both read
 // from global memory, 2 = pattern table in LDS and the (large) low rank
 // table from global memory.
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, int LPR, bool W64, bool EX>
 static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const size_t ptab = size_t(L.ham->n_ops_pad) * 16 * sizeof(double);
     if constexpr (!W64) {
         const size_t lds = hv_stage_bytes(L.ham, SECTOR);
         if (sc.stage_tables && lds <= kLdsStageBytes)
-            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 0>(L, sc, lds, st);
+            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 0, EX>(L, sc, lds, st);
     }
     if constexpr (SECTOR) {
         if (sc.stage_tables && ptab <= kLdsStageBytes)
-            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 2>(L, sc, ptab, st);
+            return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 2, EX>(L, sc, ptab, st);
     }
-    return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 1>(L, sc, 0, st);
+    return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 1, EX>(L, sc, 0, st);
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, int B, bool EX>
 static int launch_hv_l(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const bool w64 = L.ham->basis->nbits > 32;
     if (w64) {
         if constexpr (B <= 4) {
             if constexpr (B >= 2)
-                if (sc.lpr == 2) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, true>(L, sc, st);
+                if (sc.lpr == 2) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, true, EX>(L, sc, st);
             if constexpr (B >= 4)
-                if (sc.lpr == 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, true>(L, sc, st);
-            return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true>(L, sc, st);
+                if (sc.lpr == 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, true, EX>(L, sc, st);
+            return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, true, EX>(L, sc, st);
         }
         return set_error(HPHI_EINVAL, "nvec > 4 needs a space of at most 32 bits");
     }
     if constexpr (B >= 2) {
         switch (sc.lpr) {
-            case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, false>(L, sc, st);
+            case 2: return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 2, false, EX>(L, sc, st);
             case 4:
-                if constexpr (B >= 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false>(L, sc, st);
+                if constexpr (B >= 4) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 4, false, EX>(L, sc, st);
                 break;
             case 8:
-                if constexpr (B >= 8) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 8, false>(L, sc, st);
+                if constexpr (B >= 8) return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 8, false, EX>(L, sc, st);
                 break;
         }
     }
-    return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, false>(L, sc, st);
+    return launch_hv_t<S, CPLX, CCOEF, SECTOR, B, 1, false, EX>(L, sc, st);
 }
 
-template <typename S, bool CPLX, bool CCOEF, bool SECTOR>
+template <typename S, bool CPLX, bool CCOEF, bool SECTOR, bool EX>
 static int launch_hv_b(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     switch (L.nvec) {
-        case 1: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 1>(L, sc, st);
-        case 2: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 2>(L, sc, st);
-        case 4: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 4>(L, sc, st);
-        case 8: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 8>(L, sc, st);
-        case 16: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 16>(L, sc, st);
+        case 1: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 1, EX>(L, sc, st);
+        case 2: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 2, EX>(L, sc, st);
+        case 4: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 4, EX>(L, sc, st);
+        case 8: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 8, EX>(L, sc, st);
+        case 16: return launch_hv_l<S, CPLX, CCOEF, SECTOR, 16, EX>(L, sc, st);
     }
     return set_error(HPHI_EINVAL, "nvec must be 1, 2, 4, 8 or 16 (got %d)", L.nvec);
 }
 
 // ---- windowed full-space launches
-template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT>
+template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT, bool EX>
 static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
                         hipStream_t st) {
     const hphi_ham* H = L.ham;
-    static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR, NT>);
+    static const int occ = occupancy_blocks(hvw_kernel<S, CPLX, CCOEF, B, LPR, NT, EX>);
     // dynamic LDS: the pass's pattern table, then one row tile per wavefront
     constexpr int NE = (B / LPR) * (CPLX ? 2 : 1);
     constexpr int TRB = LaneLayout<S, NE, LPR>::RB;
@@ -1752,53 +1862,61 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
     A.b = L.b;
     A.stop = L.stop;
     A.partials = H->d_partials;
-    if (P->n_pass > 1 && !L.u) return set_error(HPHI_EINVAL, "multi-pass product needs an output buffer");
-    if (staged && !stage[0]) return set_error(HPHI_EINVAL, "staged product without staging buffers");
+    if constexpr (EX) {
+        A.ex = *L.ex;
+        if (P->n_pass > A.ex.n_pass) return set_error(HPHI_EINVAL, "element export: too many passes in the plan");
+    } else {
+        if (P->n_pass > 1 && !L.u) return set_error(HPHI_EINVAL, "multi-pass product needs an output buffer");
+        if (staged && !stage[0]) return set_error(HPHI_EINVAL, "staged product without staging buffers");
+    }
     for (int p = 0; p < P->n_pass; ++p) {
-        const bool next = staged && p + 1 < P->n_pass;
+        const bool next = !EX && staged && p + 1 < P->n_pass;
+        A.pass = p;
         A.kops = staged ? P->d_kopq : P->d_kop64;
         A.kop_begin = P->kop_begin[p];
         A.kop_end = P->kop_begin[p + 1];
         A.perm = P->d_perm + size_t(p) * 64;
         A.mode = (p == 0 ? 1 : 0) | (p == P->n_pass - 1 ? 2 : 0);
-        A.v = (staged && p > 0) ? stage[(p - 1) & 1] : L.v;
+        A.v = (staged && p > 0 && !EX) ? stage[(p - 1) & 1] : L.v;
         A.g_q = (staged && p > 0) ? 1 : 0;
         A.stage = next ? stage[p & 1] : nullptr;
         A.inv_next = next ? P->d_inv + size_t(p + 1) * 64 : nullptr;
-        hvw_kernel<S, CPLX, CCOEF, B, LPR, NT><<<grid, kBlock, lds_of(p), st>>>(A);
+        hvw_kernel<S, CPLX, CCOEF, B, LPR, NT, EX><<<grid, kBlock, lds_of(p), st>>>(A);
         int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
         if (rc) return rc;
     }
-    if (L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop);
+    if (!EX && L.reduce_out) {
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop, H->d_flag,
+                                                      HPHI_NONFINITE_PRODUCT);
         return check_hip(hipGetLastError(), "reduce launch");
     }
     return HPHI_OK;
 }
 
-template <typename S, bool CPLX, bool CCOEF, int B>
+template <typename S, bool CPLX, bool CCOEF, int B, bool EX>
 static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
                         hipStream_t st) {
     if constexpr (B >= 8) {
-        if (sc.nt_streams) {
+        // streaming hints change no index or value: the export takes the plain variant
+        if (sc.nt_streams && !EX) {
             switch (sc.lpr) {
-                case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, true>(L, P, sc, staged, stage, st);
-                case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, true>(L, P, sc, staged, stage, st);
-                case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, true>(L, P, sc, staged, stage, st);
+                case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, true, false>(L, P, sc, staged, stage, st);
+                case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, true, false>(L, P, sc, staged, stage, st);
+                case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, true, false>(L, P, sc, staged, stage, st);
             }
         }
         switch (sc.lpr) {
-            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, false>(L, P, sc, staged, stage, st);
-            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, false>(L, P, sc, staged, stage, st);
-            case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, false>(L, P, sc, staged, stage, st);
+            case 2: return launch_hvw_t<S, CPLX, CCOEF, B, 2, false, EX>(L, P, sc, staged, stage, st);
+            case 4: return launch_hvw_t<S, CPLX, CCOEF, B, 4, false, EX>(L, P, sc, staged, stage, st);
+            case 8: return launch_hvw_t<S, CPLX, CCOEF, B, 8, false, EX>(L, P, sc, staged, stage, st);
         }
     }
-    return launch_hvw_t<S, CPLX, CCOEF, B, 1, false>(L, P, sc, staged, stage, st);
+    return launch_hvw_t<S, CPLX, CCOEF, B, 1, false, EX>(L, P, sc, staged, stage, st);
 }
 
 // windowed product when it applies (full space, <= 32 bits, no in-place
 // extra input across several passes); returns 1 if not applicable
-template <typename S, bool CPLX, bool CCOEF>
+template <typename S, bool CPLX, bool CCOEF, bool EX>
 static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const hphi_basis* Bs = L.ham->basis;
     if (!sc.windowed || Bs->dev.sector != 0 || Bs->nbits > 32 || Bs->nbits < 6) return 1;
@@ -1807,11 +1925,13 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     if (!P) return 1;
     // several passes carry partial sums through u: they need a real output
     // buffer that is not also an input
-    if (P->n_pass > 1 && (!L.u || L.y)) return 1;
+    if (!EX && P->n_pass > 1 && (!L.u || L.y)) return 1;
     // the pattern table of a pass lives in LDS: at most kMaxPassOps operators,
-    // and with the row tiles (for rows of at most 128 bytes) and the kernel's
-    // static block-sum array within the 160 KB of a workgroup
-    const size_t tile_lds = tile_in_lds(row_bytes, 1) ? size_t(kWavesPerBlock) * 64 * row_bytes : 0;
+    // and with the row tiles (rows of at most 128 bytes with the lanes per row
+    // launch_hvw_b will use) and the kernel's static block-sum array within
+    // the 160 KB of a workgroup
+    const int lpr = (L.nvec >= 8 && (sc.lpr == 2 || sc.lpr == 4 || sc.lpr == 8)) ? sc.lpr : 1;
+    const size_t tile_lds = tile_in_lds(row_bytes, lpr) ? size_t(kWavesPerBlock) * 64 * row_bytes : 0;
     constexpr size_t static_lds = size_t(kWavesPerBlock) * kNQ * 64 * sizeof(double);
     for (int p = 0; p < P->n_pass; ++p) {
         const int n = P->kop_begin[p + 1] - P->kop_begin[p];
@@ -1820,7 +1940,7 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     }
     bool staged = sc.windowed == 2 && P->n_pass > 1;
     void* stage[2] = {nullptr, nullptr};
-    if (staged) {
+    if (staged && !EX) {
         // staging buffers are allocated on first use; never inside a graph capture
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         (void)hipStreamIsCapturing(st, &cs);
@@ -1832,22 +1952,33 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
             staged = false;
     }
     switch (L.nvec) {
-        case 1: return launch_hvw_b<S, CPLX, CCOEF, 1>(L, P, sc, staged, stage, st);
-        case 2: return launch_hvw_b<S, CPLX, CCOEF, 2>(L, P, sc, staged, stage, st);
-        case 4: return launch_hvw_b<S, CPLX, CCOEF, 4>(L, P, sc, staged, stage, st);
-        case 8: return launch_hvw_b<S, CPLX, CCOEF, 8>(L, P, sc, staged, stage, st);
-        case 16: return launch_hvw_b<S, CPLX, CCOEF, 16>(L, P, sc, staged, stage, st);
+        case 1: return launch_hvw_b<S, CPLX, CCOEF, 1, EX>(L, P, sc, staged, stage, st);
+        case 2: return launch_hvw_b<S, CPLX, CCOEF, 2, EX>(L, P, sc, staged, stage, st);
+        case 4: return launch_hvw_b<S, CPLX, CCOEF, 4, EX>(L, P, sc, staged, stage, st);
+        case 8: return launch_hvw_b<S, CPLX, CCOEF, 8, EX>(L, P, sc, staged, stage, st);
+        case 16: return launch_hvw_b<S, CPLX, CCOEF, 16, EX>(L, P, sc, staged, stage, st);
     }
     return 1;
 }
 
+template <typename S, bool CPLX, bool CCOEF, bool EX>
+static int launch_hv_s2(const HvLaunch& L, hipStream_t st) {
+    const Schedule sc = L.sched ? *L.sched : schedule_for(L.ham, L.nvec, L.dtype);
+    const int w = try_launch_hvw<S, CPLX, CCOEF, EX>(L, sc, st);
+    if (w != 1) return w;
+    if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true, EX>(L, sc, st);
+    return launch_hv_b<S, CPLX, CCOEF, false, EX>(L, sc, st);
+}
+
+// the product, or (L.ex set) the element export through the same kernels and
+// schedule; exports are instantiated for the complex storage types
 template <typename S, bool CPLX, bool CCOEF>
 static int launch_hv_s(const HvLaunch& L, hipStream_t st) {
-    const Schedule sc = L.sched ? *L.sched : schedule_for(L.ham, L.nvec, L.dtype);
-    const int w = try_launch_hvw<S, CPLX, CCOEF>(L, sc, st);
-    if (w != 1) return w;
-    if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true>(L, sc, st);
-    return launch_hv_b<S, CPLX, CCOEF, false>(L, sc, st);
+    if (L.ex) {
+        if constexpr (CPLX) return launch_hv_s2<S, CPLX, CCOEF, true>(L, st);
+        return set_error(HPHI_EINVAL, "element export: use a complex storage type (C128 or C64)");
+    }
+    return launch_hv_s2<S, CPLX, CCOEF, false>(L, st);
 }
 
 // ---- dense-block product launch
@@ -1890,7 +2021,8 @@ static int launch_cma_stages(const HvLaunch& L, const CmaPlan* P, hipStream_t st
     }
     if (!L.reduce_out) return HPHI_OK;
     constexpr int B = RC / (CPLX ? 2 : 1);
-    reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, int(g), kNQ * B, L.reduce_out, nullptr);
+    reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, int(g), kNQ * B, L.reduce_out, nullptr, H->d_flag,
+                                                      HPHI_NONFINITE_PRODUCT);
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
@@ -1951,16 +2083,11 @@ int launch_hv(const HvLaunch& L, hipStream_t st) {
     return set_error(HPHI_EINVAL, "bad dtype %d", L.dtype);
 }
 
-int launch_elements(const hphi_ham* H, int64_t row0, int64_t nrows, int cap, int64_t* cols, double* re, double* im,
-                    int32_t* term, int32_t* counts, hipStream_t st) {
-    const int64_t blocks = (nrows + 255) / 256;
-    if (H->basis->dev.sector != 0)
-        elements_kernel<true><<<dim3(unsigned(blocks)), 256, 0, st>>>(H->basis->dev, H->d_ops, int(H->ops.size()),
-                                                                        row0, nrows, cap, cols, re, im, term, counts);
-    else
-        elements_kernel<false><<<dim3(unsigned(blocks)), 256, 0, st>>>(H->basis->dev, H->d_ops, int(H->ops.size()),
-                                                                         row0, nrows, cap, cols, re, im, term, counts);
-    return check_hip(hipGetLastError(), "elements_kernel launch");
+int launch_elements_compact(const hphi_ham* H, const ExportArgs& ex, int cap, int64_t* cols, double* re, double* im,
+                            int32_t* term, int32_t* counts, hipStream_t st) {
+    const int64_t blocks = (ex.nrows + 255) / 256;
+    elements_compact_kernel<<<dim3(unsigned(blocks)), 256, 0, st>>>(ex, H->d_ops, cap, cols, re, im, term, counts);
+    return check_hip(hipGetLastError(), "elements_compact launch");
 }
 
 int launch_rank(const hphi_basis* b, const uint64_t* cfg, int64_t* idx, int64_t n, hipStream_t st) {
@@ -1989,7 +2116,7 @@ static int stream_grid(int64_t n) {
 }
 
 int launch_copy_norm(const void* src, void* dst, int64_t n, int dtype, double* partials, int grid, double* red,
-                     hipStream_t st) {
+                     int32_t* flag, hipStream_t st) {
     const int64_t ns = n * (dtype_complex(dtype) ? 2 : 1);
     if (grid <= 0) grid = stream_grid(ns);
     if (dtype == HPHI_F64 || dtype == HPHI_C128)
@@ -1998,13 +2125,13 @@ int launch_copy_norm(const void* src, void* dst, int64_t n, int dtype, double* p
         copy_norm_kernel<float><<<grid, 256, 0, st>>>((const float*)src, (float*)dst, ns, partials);
     int rc = check_hip(hipGetLastError(), "copy_norm launch");
     if (rc) return rc;
-    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, red, nullptr);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, red, nullptr, flag, HPHI_NONFINITE_NORM);
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
 int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const double* c2, void* acc,
                           const double* ecoef, double* partials, int grid, double* red, const int* stop,
-                          hipStream_t st) {
+                          int32_t* flag, hipStream_t st) {
     const int64_t ns = n * (dtype_complex(dtype) ? 2 : 1);
     if (grid <= 0) grid = stream_grid(ns);
     if (dtype == HPHI_F64 || dtype == HPHI_C128)
@@ -2015,7 +2142,7 @@ int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const do
                                                            partials, stop);
     int rc = check_hip(hipGetLastError(), "lanczos_update launch");
     if (rc) return rc;
-    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, red, stop);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, red, stop, flag, HPHI_NONFINITE_NORM);
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
@@ -2025,7 +2152,7 @@ int launch_lincomb(double* w, const double* x, const double* y, int64_t n, doubl
     lincomb_kernel<<<grid, 256, 0, st>>>(w, x, y, n, a, b, partials);
     int rc = check_hip(hipGetLastError(), "lincomb launch");
     if (rc || !norm2) return rc;
-    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, norm2, nullptr);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(partials, grid, 1, norm2, nullptr, nullptr, 0);
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
@@ -2043,6 +2170,17 @@ int launch_expect(const double* red, double* out, int nvec, hipStream_t st) {
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k, hipStream_t st) {
     tpq_obs_kernel<<<1, 64, 0, st>>>(red, obs, nvec, n_sites, l, k);
     return check_hip(hipGetLastError(), "tpq_obs launch");
+}
+
+int launch_tpq_run_init(TpqRunState* s, int k0, hipStream_t st) {
+    tpq_run_init_kernel<<<1, 64, 0, st>>>(s, k0);
+    return check_hip(hipGetLastError(), "tpq_run_init launch");
+}
+
+int launch_tpq_obs_run(const double* red, TpqRunState* s, double* obs_log, int nvec, double n_sites, double l,
+                       hipStream_t st) {
+    tpq_obs_run_kernel<<<1, 64, 0, st>>>(red, s, obs_log, nvec, n_sites, l);
+    return check_hip(hipGetLastError(), "tpq_obs_run launch");
 }
 
 int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipStream_t st) {
@@ -2162,7 +2300,7 @@ int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out) {
     const size_t r_off = p_off + size_t(P.grid) * kNQ * sizeof(double);
     const size_t total = r_off + size_t(n) * sizeof(RedDesc);
     char* mem = nullptr;
-    if (hipMalloc(&mem, total) != hipSuccess) return set_error(HPHI_ENOMEM, "hv_multi_prepare: device memory");
+    if (int rc = dev_alloc((void**)&mem, total, "hv_multi_prepare")) return rc;
     std::vector<HvArgs> args(n);
     std::vector<RedDesc> red(n);
     double* partials = reinterpret_cast<double*>(mem + p_off);
@@ -2187,6 +2325,7 @@ int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out) {
         red[p].pad = 0;
         red[p].out = L.reduce_out;
         red[p].stop = L.stop;
+        red[p].flag = L.ham->d_flag;
     }
     hipError_t e = hipMemcpy(mem, args.data(), a_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mem + b_off, begin.data(), size_t(n + 1) * 4, hipMemcpyHostToDevice);
@@ -2226,7 +2365,7 @@ int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int d
     const size_t r_off = p_off + size_t(P.grid) * sizeof(double);
     const size_t total_b = r_off + size_t(n) * sizeof(RedDesc);
     char* mem = nullptr;
-    if (hipMalloc(&mem, total_b) != hipSuccess) return set_error(HPHI_ENOMEM, "upd_multi_prepare: device memory");
+    if (int rc = dev_alloc((void**)&mem, total_b, "upd_multi_prepare")) return rc;
     std::vector<UpdDesc> d(descs, descs + n);
     std::vector<RedDesc> red(n);
     double* partials = reinterpret_cast<double*>(mem + p_off);
@@ -2237,6 +2376,7 @@ int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int d
         red[p].pad = 0;
         red[p].out = red_out[p];
         red[p].stop = d[p].stop;
+        red[p].flag = d[p].flag;
     }
     hipError_t e = hipMemcpy(mem, d.data(), d_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mem + b_off, begin.data(), size_t(n + 1) * 4, hipMemcpyHostToDevice);

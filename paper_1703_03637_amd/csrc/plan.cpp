@@ -167,11 +167,15 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
             if (!in[b]) P->perm[size_t(p) * 64 + k++] = b;
     }
     std::vector<DevOp> sorted;
+    std::vector<int> sorted_idx;     // index of each sorted operator in the Hamiltonian's list
     P->op_begin.assign(P->n_pass + 1, 0);
     for (int p = 0; p < P->n_pass; ++p) {
         P->op_begin[p] = int(sorted.size());
         for (int o = 0; o < n_ops; ++o)
-            if (pass_of[o] == p) sorted.push_back(ops[o]);
+            if (pass_of[o] == p) {
+                sorted.push_back(ops[o]);
+                sorted_idx.push_back(o);
+            }
     }
     P->op_begin[P->n_pass] = int(sorted.size());
     // compact records, padded per pass to a multiple of 4
@@ -182,6 +186,7 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
         for (int o = P->op_begin[p]; o < P->op_begin[p + 1]; ++o) {
             const DevOp& d = sorted[o];
             KOp<double> b{};
+            b.op = sorted_idx[o];
             b.xm = d.has_off ? uint32_t(d.xmask) : 0u;
             b.sm = uint32_t(d.smask);
             b.bi = d.bi;
@@ -193,10 +198,18 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
             }
             k64.push_back(b);
         }
-        while (k64.size() % 4) k64.push_back(KOp<double>{});
+        while (k64.size() % 4) {
+            KOp<double> pad{};
+            pad.op = -1;
+            k64.push_back(pad);
+        }
     }
     P->kop_begin[P->n_pass] = int(k64.size());
-    if (k64.empty()) k64.push_back(KOp<double>{});
+    if (k64.empty()) {
+        KOp<double> pad{};
+        pad.op = -1;
+        k64.push_back(pad);
+    }
     // inverse permutations, and the flip masks of passes after the first in
     // processing-index bits (a bit permutation commutes with XOR, so the
     // partner of processing index q is q ^ perm^-1(xmask))
@@ -220,11 +233,11 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
             kq[o].xm = m;
         }
     const size_t kb = k64.size() * sizeof(KOp<double>);
-    if (hipMalloc(&P->d_kop64, kb) != hipSuccess) {
+    if (dev_alloc((void**)&P->d_kop64, kb, "pass plan")) {
         delete P;
         return nullptr;
     }
-    if (hipMalloc(&P->d_kopq, kb) != hipSuccess || hipMalloc(&P->d_inv, P->inv.size() * 4) != hipSuccess) {
+    if (dev_alloc((void**)&P->d_kopq, kb, "pass plan") || dev_alloc((void**)&P->d_inv, P->inv.size() * 4, "pass plan")) {
         (void)hipFree(P->d_kop64);
         if (P->d_kopq) (void)hipFree(P->d_kopq);
         delete P;
@@ -234,7 +247,7 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
     (void)hipMemcpy(P->d_kopq, kq.data(), kb, hipMemcpyHostToDevice);
     (void)hipMemcpy(P->d_inv, P->inv.data(), P->inv.size() * 4, hipMemcpyHostToDevice);
     const size_t ob = std::max<size_t>(1, sorted.size()) * sizeof(DevOp);
-    if (hipMalloc(&P->d_ops, ob) != hipSuccess || hipMalloc(&P->d_perm, P->perm.size() * 4) != hipSuccess) {
+    if (dev_alloc((void**)&P->d_ops, ob, "pass plan") || dev_alloc((void**)&P->d_perm, P->perm.size() * 4, "pass plan")) {
         if (P->d_ops) (void)hipFree(P->d_ops);
         (void)hipFree(P->d_kop64);
         (void)hipFree(P->d_kopq);
@@ -287,7 +300,7 @@ int get_stage_buffers(const hphi_ham* ham, size_t bytes, int count, void** out) 
             if (H->d_stage[i]) (void)hipFree(H->d_stage[i]);
             H->d_stage[i] = nullptr;
             H->stage_bytes[i] = 0;
-            if (hipMalloc(&H->d_stage[i], bytes) != hipSuccess) {
+            if (dev_alloc(&H->d_stage[i], bytes, "staging buffer")) {
                 H->d_stage[i] = nullptr;
                 return 1;
             }

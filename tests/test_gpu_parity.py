@@ -126,6 +126,83 @@ def test_element_lists_hubbard_4x3_sampled_rows():
         _compare_elements([g], [o], exact_values=True)
 
 
+def _export_lists(ham, nrows, nvec, dtype, cap=64):
+    cols, re, im, term, counts = hp.hphi_hv_elements(ham, 0, nrows, cap, nvec=nvec, dtype=dtype)
+    cols, re, im, term, counts = (x.cpu().numpy() for x in (cols, re, im, term, counts))
+    assert counts.max() <= cap
+    out = []
+    for r in range(nrows):
+        d = {}
+        for k in range(counts[r]):
+            key = (int(cols[r, k]), int(term[r, k]))
+            assert key not in d, "duplicate (col, term) from one row"
+            d[key] = complex(re[r, k], im[r, k])
+        out.append(d)
+    return out
+
+
+EXPORT_LAYOUTS = [(1, torch.complex128, 0), (16, torch.complex64, 4), (16, torch.complex64, 8),
+                  (8, torch.complex128, 2), (16, torch.complex128, 2), (4, torch.complex64, 1)]
+
+
+@pytest.mark.parametrize("nvec,dtype,lpr", EXPORT_LAYOUTS)
+@pytest.mark.parametrize("windowed,window_kb,passes", [(0, 2048, 1), (1, 2048, 1), (1, 1, 3), (1, 2, 2),
+                                                       (2, 1, 3), (2, 2, 2)])
+@pytest.mark.parametrize("name", ["kh_honeycomb12", "spin_full_complex", "spin_full_real", "ferm_full"])
+def test_element_export_full_space_product_paths(monkeypatch, name, windowed, window_kb, passes, nvec, dtype, lpr):
+    """Sec. 3.3 decode exported by the product kernels themselves on full spaces: the single-pass
+    kernel and the windowed kernel with 1 to 3 passes, gathering from v or from staged copies (flip
+    masks in processing-index bits), partners inside the 64-row tile read from the LDS tile (rows of
+    at most 128 bytes, at most 4 lanes per row) or exchanged between lanes (8 lanes per row, or
+    256-byte rows).  Index, term and sign lists bit-exact against the oracle."""
+    print(f"[gpu] export {name} windowed={windowed} kb={window_kb} passes={passes} nvec={nvec} {dtype} lpr={lpr}",
+          flush=True)
+    for k, val in (("HPHI_WINDOWED", windowed), ("HPHI_L2_WINDOW_KB", window_kb), ("HPHI_PASSES", passes),
+                   ("HPHI_LPR", lpr)):
+        monkeypatch.setenv(k, str(val))
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    gpu = _export_lists(ham, basis.dim, nvec, dtype)
+    ora = oh.row_elements(desc, terms, np.arange(len(st)), st)
+    _compare_elements(gpu, [ora[i] for i in range(len(st))], exact_values=False)
+
+
+@pytest.mark.parametrize("nvec,dtype,lpr", [(1, torch.complex128, 0), (4, torch.complex64, 2),
+                                            (4, torch.complex128, 4), (16, torch.complex64, 8),
+                                            (2, torch.complex64, 1)])
+@pytest.mark.parametrize("stage", [0, 1])
+@pytest.mark.parametrize("name", ["spin_sz_dm", "spin_sz_split3", "ferm_nupndn", "ferm_ntot", "hubbard_3x3"])
+def test_element_export_sector_product_paths(monkeypatch, name, stage, nvec, dtype, lpr):
+    """The sector product's own decode (tile-uniform high-half rank, the row's own low rank when an
+    operator leaves the low half alone, the low rank table in LDS or global memory, fermion parity)
+    exported for every row: bit-exact against the oracle."""
+    print(f"[gpu] export sector {name} stage={stage} nvec={nvec} {dtype} lpr={lpr}", flush=True)
+    monkeypatch.setenv("HPHI_STAGE_TABLES", str(stage))
+    monkeypatch.setenv("HPHI_LPR", str(lpr))
+    desc, terms, basis, ham = _case(name)
+    st = ob.states(desc)
+    gpu = _export_lists(ham, basis.dim, nvec, dtype)
+    ora = oh.row_elements(desc, terms, np.arange(len(st)), st)
+    _compare_elements(gpu, [ora[i] for i in range(len(st))], exact_values=desc.particle == "fermion")
+
+
+def test_element_export_row_windows_and_errors():
+    """Row windows that start and end inside tiles and high halves give the rows of the full export;
+    real storage types, too many rows and bad ranges are rejected."""
+    desc, terms, basis, ham = _case("hubbard_3x3")
+    full = _export_lists(ham, basis.dim, 1, torch.complex128)
+    for r0, n in ((0, 1), (37, 100), (basis.dim - 70, 70), (63, 2), (1000, 1)):
+        cols, re, im, term, counts = (x.cpu().numpy() for x in hp.hphi_hv_elements(ham, r0, n, 64))
+        for r in range(n):
+            got = {(int(cols[r, k]), int(term[r, k])): complex(re[r, k], im[r, k]) for k in range(counts[r])}
+            assert got == full[r0 + r]
+    for bad in (dict(nvec=3), dict(dtype=torch.float64)):
+        with pytest.raises((hp.HphiError, KeyError)):
+            hp.hphi_hv_elements(ham, 0, 4, 8, **bad)
+    with pytest.raises(hp.HphiError):
+        hp.hphi_hv_elements(ham, basis.dim - 1, 2, 8)
+
+
 def _abs_bound(desc, terms, st, v):
     H = oh.sparse_h(desc, terms, st)
     Ha = abs(H)
@@ -546,16 +623,19 @@ def test_hv_windowed_tile_partners(monkeypatch, lpr, n_sites, windowed, passes, 
         assert abs(red[1, k] - want) <= 10 * tol * np.linalg.norm(vin[:, k]) * np.linalg.norm(hx[:, k]), k
 
 
+@pytest.mark.parametrize("lpr", [4, 8])
 @pytest.mark.parametrize("dt,nvec", [(torch.complex64, 16), (torch.complex128, 8)])
-def test_hv_windowed_pass_too_large_for_lds_falls_back(monkeypatch, dt, nvec):
-    """990 operators with complex elements in one windowed pass: the pattern table (127 KB), the row
-    tiles of 128-byte rows (32 KB) and the kernel's block sums exceed a workgroup's LDS, so the
-    product takes the single-pass kernel instead, with the same result."""
-    print(f"[gpu] windowed pass over the LDS limit dt={dt} nvec={nvec}", flush=True)
+def test_hv_windowed_pass_too_large_for_lds_falls_back(monkeypatch, dt, nvec, lpr):
+    """990 operators with complex elements in one windowed pass: the pattern table (127 KB).  With
+    4 lanes per row the row tiles of 128-byte rows (32 KB) and the kernel's block sums exceed a
+    workgroup's LDS, so the product takes the single-pass kernel instead; with 8 lanes per row the
+    windowed kernel keeps no row tile and the pass fits (table + block sums = 135 KB).  Both give the
+    oracle's result."""
+    print(f"[gpu] windowed pass near the LDS limit dt={dt} nvec={nvec} lpr={lpr}", flush=True)
     monkeypatch.setenv("HPHI_WINDOWED", "1")
     monkeypatch.setenv("HPHI_PASSES", "1")
     monkeypatch.setenv("HPHI_L2_WINDOW_KB", "65536")
-    monkeypatch.setenv("HPHI_LPR", "4")
+    monkeypatch.setenv("HPHI_LPR", str(lpr))
     desc = BasisDesc("spin", 12)
     rng = np.random.default_rng(17)
     terms = [L.Term(L.SPIN_FIELD, k % 12, -1, tuple(float(x) for x in rng.uniform(-0.05, 0.05, 3))) for k in range(980)]

@@ -72,7 +72,7 @@ def test_entry_points_reject_null_handles(lib):
     opts = L.HvOptsC(1.0, 0.0, None, None)
     assert lib.hphi_hv(None, None, None, 1, 0, C.byref(opts), None) == L.HPHI_EINVAL
     assert lib.hphi_tpq_step(None, None, None, 1, 0, 1.5, 1, None, None, None) == L.HPHI_EINVAL
-    assert lib.hphi_hv_elements(None, 0, 1, 4, None, None, None, None, None, None) == L.HPHI_EINVAL
+    assert lib.hphi_hv_elements(None, 0, 1, 4, 1, L.HPHI_C128, None, None, None, None, None, None) == L.HPHI_EINVAL
     assert lib.hphi_basis_dim(None, None) == L.HPHI_EINVAL
     lo = L.LanczosOptsC(10, 0, 0, 0, 0.0)
     assert lib.hphi_lanczos(None, 1, C.byref(lo), None, None, None, None, None) == L.HPHI_EINVAL
@@ -101,3 +101,21 @@ def test_product_path_does_not_import_oracle():
             "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), 'oracle imported'")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_injected_allocation_failure_is_enomem(lib, monkeypatch):
+    """The allocation hook (HPHI_FAIL_ALLOC=N fails the N-th allocation) turns the first allocation of
+    a basis build into HPHI_ENOMEM before any device call, with a message."""
+    from paper_1703_03637_amd import _lib as L
+    desc = L.BasisDescC(L.HPHI_SPIN_HALF, 8, L.HPHI_SECTOR_SZ, 0, 0, 0, 0, 0)
+    out = C.c_void_p()
+    monkeypatch.setenv("HPHI_FAIL_ALLOC", "1")
+    assert lib.hphi_basis_build(C.byref(desc), C.byref(out)) == L.HPHI_ENOMEM
+    assert b"allocation" in lib.hphi_last_error()
+    assert out.value is None
+
+
+def test_nonfinite_query_rejects_null(lib):
+    from paper_1703_03637_amd import _lib as L
+    f = C.c_int32()
+    assert lib.hphi_ham_nonfinite(None, C.byref(f), 0, None) == L.HPHI_EINVAL

@@ -618,3 +618,52 @@ def test_c_oracle_c64_rows_equal_upcast_rows(sector):
     b = c_oracle.rows_hv(terms, rows, v.astype(np.complex128), states=states)
     assert np.array_equal(a, b)
     assert np.abs(a).max() > 0
+
+
+def test_lowest_eigenvalue_matches_dense():
+    """The sparse eigensolver step of the oracle against dense diagonalization (sectors of a
+    12-site chain and a Hubbard cluster)."""
+    for desc, terms in (
+            (BasisDesc("spin", 12, "sz", two_sz=0), [L.heisenberg_bond(i, j) for i, j in L.chain_bonds(12)]),
+            (BasisDesc("spin", 12, "sz", two_sz=10), [L.heisenberg_bond(i, j) for i, j in L.chain_bonds(12)]),
+            (BasisDesc("fermion", 6, "nupndn", n_up=3, n_dn=3), L.hubbard_terms(L.rect_bonds(3, 2), 6, 1.0, 4.0))):
+        H = oh.sparse_h(desc, terms)
+        assert abs(osv.lowest_eigenvalue(H) - np.linalg.eigvalsh(H.toarray())[0]) < 1e-11
+
+
+def test_golden_oracle_energies_pinned():
+    """tests/golden/oracle_energies.json (written by make_oracle_energies.py from the oracle alone):
+    its U = 0 Hubbard energy must equal the free-fermion closed form, the fully polarized tri24 sector
+    72/4 exactly, the dimensions the binomials, and the sector energies must rise with Sz beyond
+    Sz = 0 (the ground state of an antiferromagnet on a finite torus has the lowest total spin)."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_energies.json")))
+    lv = sorted(-2 * math.cos(math.pi * m / 5) - 2 * math.cos(math.pi * n / 4) for m in range(1, 5)
+                for n in range(1, 4))
+    assert abs(g["hubbard_4x3_U0"]["e0"] - 2 * sum(lv[:6])) < 1e-10
+    assert g["hubbard_4x3_U8"]["dim"] == comb(12, 6) ** 2
+    assert g["hubbard_4x3_U0"]["e0"] < g["hubbard_4x3_U8"]["e0"] < 0
+    tri = g["tri24"]
+    assert sorted(int(k) for k in tri) == list(range(13))
+    for sz in range(13):
+        assert tri[str(sz)]["dim"] == comb(24, 12 + sz)
+    assert tri["12"]["e0"] == 18.0
+    e = [tri[str(sz)]["e0"] for sz in range(13)]
+    assert all(a < b for a, b in zip(e, e[1:]))
+
+
+def test_splitmix_stream_and_on_demand_rows():
+    """The on-demand input vector of the C oracle (for spaces too large for host memory): its
+    generator reproduces the published SplitMix64 outputs for seed 0, and rows computed with v
+    evaluated on demand equal the counted-rank rows on the same vector stored explicitly."""
+    from oracle import c_oracle
+    sm = c_oracle.lib().oracle_splitmix64
+    assert [sm(0, i) for i in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    desc = BasisDesc("spin", 12, "sz", two_sz=2)
+    terms = [L.heisenberg_bond(i, j, 1.0) for i, j in L.kagome_bonds(2, 2)]
+    st = ob.states(desc)
+    nvec, seed = 3, 1234
+    raw = np.array([sm(seed, i) for i in range(len(st) * nvec)], dtype=np.uint64)
+    v = ((raw >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 * 2.0 - 1.0).reshape(len(st), nvec)
+    a = c_oracle.rows_hv_counted_ondemand(desc, terms, st, seed, nvec)
+    b = c_oracle.rows_hv_counted(desc, terms, st, v.astype(np.complex128))
+    assert np.array_equal(a, b.real) and np.all(b.imag == 0)
