@@ -422,6 +422,26 @@ int hphi_tpq_run(const hphi_ham* ham, void* psi_a, void* psi_b, int64_t nvec, in
                  int32_t k0, int32_t n_steps, const double* in_scale, double* obs_log, int32_t use_graph,
                  void* stream);
 
+/* hphi_tpq_run for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, steps, obs_log layout and final-state placement as
+ * hphi_tpq_run, with these differences:
+ *   - allocates nothing: the run's device state (step index, step counter
+ *     and the scales of the last two states, 272 bytes) lives in a static
+ *     device array of the library, one per GPU, held until the process ends;
+ *     the product uses only pass plans and staging buffers that earlier calls
+ *     on this ham built (else it takes the single-pass kernel, which needs
+ *     none), and the ham's own reduction workspace;
+ *   - launches every step eagerly on `stream` and returns without
+ *     synchronizing, so the whole run may itself be captured into a graph;
+ *   - maximum: nvec <= 16 (the static state holds 16 scales); larger values
+ *     return HPHI_EINVAL.
+ * The static state is shared by every call on a GPU and keeps the last
+ * call's contents (each call resets its counters first): calls that overlap
+ * in time on one GPU race, even on different hams. */
+int hphi_tpq_run_noalloc(const hphi_ham* ham, void* psi_a, void* psi_b, int64_t nvec, int32_t dtype, double l,
+                         int32_t k0, int32_t n_steps, const double* in_scale, double* obs_log, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Message of the last error on this thread ("" if none). */

@@ -24,6 +24,7 @@ from .binding import (  # noqa: F401
     hphi_lanczos,
     hphi_tpq_step,
     hphi_tpq_run,
+    hphi_tpq_run_noalloc,
     version,
 )
 from ._lib import HphiError, LIB_PATH  # noqa: F401

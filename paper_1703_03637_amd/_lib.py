@@ -99,6 +99,8 @@ _SIGS = {
                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_tpq_run": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                       C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "hphi_tpq_run_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                              C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "hphi_cg_refine": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(CgOptsC), C.c_void_p,
                         C.POINTER(CgResultC), C.c_void_p], C.c_int),
     "hphi_expect": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),

@@ -327,3 +327,17 @@ def hphi_tpq_run(ham: Ham, psi_a: torch.Tensor, psi_b: torch.Tensor, l: float, k
                                int(k0), int(n_steps), _ptr(in_scale), _ptr(obs_log), int(bool(use_graph)),
                                _stream()))
     return obs_log
+
+
+def hphi_tpq_run_noalloc(ham: Ham, psi_a: torch.Tensor, psi_b: torch.Tensor, l: float, k0: int, n_steps: int,
+                         obs_log: torch.Tensor, in_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """hphi_tpq_run without any device allocation (static device state; no graph, no synchronization):
+    obs_log must be a preallocated contiguous float64 device tensor of n_steps*4*nvec entries."""
+    nv = _nvec(psi_a, ham.dim)
+    if psi_b.shape != psi_a.shape or psi_b.dtype != psi_a.dtype:
+        raise ValueError("psi_b must match psi_a")
+    if obs_log.dtype != torch.float64 or obs_log.numel() < 4 * nv * n_steps or not obs_log.is_contiguous():
+        raise ValueError("obs_log must be contiguous float64 with n_steps*4*nvec entries")
+    check(L.lib().hphi_tpq_run_noalloc(C.c_void_p(ham.handle), _ptr(psi_a), _ptr(psi_b), nv, _dtype_code(psi_a),
+                                       float(l), int(k0), int(n_steps), _ptr(in_scale), _ptr(obs_log), _stream()))
+    return obs_log

@@ -316,6 +316,44 @@ extern "C" int hphi_tpq_run(const hphi_ham* ham, void* psi_a, void* psi_b, int64
     return rc ? rc : check_hip(e, "hphi_tpq_run sync");
 }
 
+extern "C" int hphi_tpq_run_noalloc(const hphi_ham* ham, void* psi_a, void* psi_b, int64_t nvec, int32_t dtype,
+                                    double l, int32_t k0, int32_t n_steps, const double* in_scale, double* obs_log,
+                                    void* stream) {
+    if (!ham || !psi_a || !psi_b || !obs_log) return set_error(HPHI_EINVAL, "hphi_tpq_run_noalloc: null argument");
+    if (psi_a == psi_b) return set_error(HPHI_EINVAL, "hphi_tpq_run_noalloc: the two state buffers must differ");
+    if (!valid_nvec(nvec) || nvec > kMaxNvec)
+        return set_error(HPHI_EINVAL, "hphi_tpq_run_noalloc: nvec must be 1, 2, 4, 8 or 16 (the static state holds "
+                                      "the scales of at most %d samples)", kMaxNvec);
+    if (!valid_dtype(dtype)) return set_error(HPHI_EINVAL, "hphi_tpq_run_noalloc: bad dtype");
+    if (ham->is_complex && !dtype_complex(dtype))
+        return set_error(HPHI_EDTYPE, "hphi_tpq_run_noalloc: complex Hamiltonian with real storage");
+    if (k0 < 1 || n_steps < 0 || !std::isfinite(l))
+        return set_error(HPHI_EINVAL, "hphi_tpq_run_noalloc: need k0 >= 1, n_steps >= 0 and finite l");
+    if (n_steps == 0) return HPHI_OK;
+    TpqRunState* S = nullptr;
+    if (int rc = tpq_static_state(&S)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const double ns = double(ham->n_sites);
+    int rc = launch_tpq_run_init(S, k0, st);
+    for (int j = 0; !rc && j < n_steps; ++j) {
+        const int parity = j & 1;
+        HvLaunch L{};
+        L.ham = ham;
+        L.v = parity ? psi_b : psi_a;
+        L.u = parity ? psi_a : psi_b;
+        L.sx = j == 0 ? in_scale : S->scale[parity ^ 1];
+        L.a = -1.0 / ns;
+        L.b = l;
+        L.nvec = int(nvec);
+        L.dtype = dtype;
+        L.reduce_out = ham->d_red;
+        L.no_alloc = true;
+        rc = launch_hv(L, st);
+        if (!rc) rc = launch_tpq_obs_run(ham->d_red, S, obs_log, int(nvec), ns, l, st);
+    }
+    return rc;
+}
+
 // ---------------------------------------------------------------- Lanczos
 
 namespace {

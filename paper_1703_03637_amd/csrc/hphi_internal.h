@@ -225,6 +225,7 @@ struct HvLaunch {
     double* reduce_out;      // device [kNQ * nvec] or nullptr (quantity-major)
     const Schedule* sched;   // nullptr: the tuned or default schedule
     const ExportArgs* ex;    // non-null: element export instead of the product
+    bool no_alloc;           // allocate nothing: only plans and staging buffers that exist already
 };
 Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype);
 int launch_hv(const HvLaunch& L, hipStream_t st);
@@ -256,6 +257,10 @@ struct TpqRunState {
     double scale[2][kMaxNvec];
 };
 int launch_tpq_run_init(TpqRunState* s, int k0, hipStream_t st);
+// The device state of the allocation-free TPQ run: a file-scope static
+// device array of one TpqRunState, its address on the current device
+// (resolved once per device).  Returns an error code or HPHI_OK.
+int tpq_static_state(TpqRunState** out);
 int launch_tpq_obs_run(const double* red, TpqRunState* s, double* obs_log, int nvec, double n_sites, double l,
                        hipStream_t st);
 
@@ -341,7 +346,8 @@ int get_cma_plan(const hphi_ham* ham, int M, const CmaPlan** out);
 int launch_hv_cma(const HvLaunch& L, const CmaPlan* P, hipStream_t st);
 
 // pass plan of the windowed product (plan.cpp); nullptr if not applicable
-const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes);
+// may_build = false: only a plan built earlier (no allocation)
+const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes, bool may_build = true);
 // staging buffers of at least `bytes` each (grown on demand, kept with the
 // Hamiltonian); returns nonzero if they cannot be had
 int get_stage_buffers(const hphi_ham* ham, size_t bytes, int count, void** out);

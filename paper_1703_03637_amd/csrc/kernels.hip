@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdlib>
 #include <vector>
 
@@ -1921,7 +1922,7 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     const hphi_basis* Bs = L.ham->basis;
     if (!sc.windowed || Bs->dev.sector != 0 || Bs->nbits > 32 || Bs->nbits < 6) return 1;
     const int row_bytes = L.nvec * int(sizeof(S)) * (CPLX ? 2 : 1);
-    const PassPlan* P = get_plan(L.ham, row_bytes, sc.window_kb, sc.max_passes);
+    const PassPlan* P = get_plan(L.ham, row_bytes, sc.window_kb, sc.max_passes, !L.no_alloc);
     if (!P) return 1;
     // several passes carry partial sums through u: they need a real output
     // buffer that is not also an input
@@ -1948,7 +1949,7 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
         const int count = P->n_pass > 2 ? 2 : 1;
         bool have = true;
         for (int i = 0; i < count; ++i) have = have && L.ham->stage_bytes[i] >= bytes;
-        if ((cs != hipStreamCaptureStatusNone && !have) || get_stage_buffers(L.ham, bytes, count, stage))
+        if (((cs != hipStreamCaptureStatusNone || L.no_alloc) && !have) || get_stage_buffers(L.ham, bytes, count, stage))
             staged = false;
     }
     switch (L.nvec) {
@@ -2170,6 +2171,28 @@ int launch_expect(const double* red, double* out, int nvec, hipStream_t st) {
 int launch_tpq_obs(const double* red, double* obs, int nvec, double n_sites, double l, int k, hipStream_t st) {
     tpq_obs_kernel<<<1, 64, 0, st>>>(red, obs, nvec, n_sites, l, k);
     return check_hip(hipGetLastError(), "tpq_obs launch");
+}
+
+// The allocation-free TPQ run keeps its state here: one per device, for the
+// life of the process (272 bytes).  Host code never names it directly: the
+// name is a host-side stand-in, so its device address is resolved per device.
+static __device__ __align__(256) TpqRunState scratch;
+
+int tpq_static_state(TpqRunState** out) {
+    static std::mutex mu;
+    static TpqRunState* addr[64] = {};
+    int dev = 0;
+    if (int rc = check_hip(hipGetDevice(&dev), "hphi_tpq_run_noalloc: current device")) return rc;
+    if (dev < 0 || dev >= 64) return set_error(HPHI_EDEVICE, "hphi_tpq_run_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (int rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hphi_tpq_run_noalloc: state address"))
+            return rc;
+        addr[dev] = static_cast<TpqRunState*>(p);
+    }
+    *out = addr[dev];
+    return HPHI_OK;
 }
 
 int launch_tpq_run_init(TpqRunState* s, int k0, hipStream_t st) {

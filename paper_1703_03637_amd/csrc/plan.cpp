@@ -262,12 +262,13 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
 
 }  // namespace
 
-const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes) {
+const PassPlan* get_plan(const hphi_ham* ham, int row_bytes, int window_kb, int max_passes, bool may_build) {
     hphi_ham* H = const_cast<hphi_ham*>(ham);
     std::lock_guard<std::mutex> lock(H->plan_mu);
     for (PassPlan* p : H->plans)
         if (p->row_bytes == row_bytes && p->window_kb == window_kb && p->max_passes == max_passes)
             return p->n_pass > 0 ? p : nullptr;
+    if (!may_build) return nullptr;
     PassPlan* p = build_plan(H, row_bytes, window_kb, max_passes);
     if (p && getenv("HPHI_DEBUG")) {
         fprintf(stderr, "[hphi] plan row_bytes=%d window_kb=%d window_bits=%d passes=%d ops/pass:", row_bytes,
