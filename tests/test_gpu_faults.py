@@ -136,8 +136,9 @@ def test_lanczos_nonfinite_start_vector_is_reported(batched):
     with pytest.raises(hp.HphiError) as ei:
         hp.hphi_lanczos(hams, x0s, 20)
     assert ei.value.code == _lib.HPHI_ENONFINITE
-    # the next run on a finite start vector clears the word and succeeds
-    x0s[0][7] = 0.25
+    # the next run on finite start vectors clears the word and succeeds
+    for x in x0s:
+        x[7] = 0.25
     res = hp.hphi_lanczos(hams, x0s, 20)
     assert np.isfinite(res[0]["e0_refined"])
 

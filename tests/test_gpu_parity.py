@@ -75,8 +75,16 @@ def _gpu_elements(ham, rows0, nrows, cap=64):
     return out
 
 
-def _compare_elements(gpu, ora, exact_values):
+def _compare_elements(gpu, ora, exact_values, diag_tol=None):
+    """Element lists per row: the off-diagonal (col, term) sets, signs and values; with diag_tol the
+    diagonal (a sum of the operators' diagonal parts, term -1) is compared as a number within diag_tol
+    (a multi-pass product sums it pass by pass, so it may differ in the last bits or vanish in one
+    order and not the other)."""
     for r, (g, o) in enumerate(zip(gpu, ora)):
+        if diag_tol is not None:
+            g, o = dict(g), dict(o)
+            gd, od = g.pop((r + _compare_elements.row0, -1), 0.0), o.pop((r + _compare_elements.row0, -1), 0.0)
+            assert abs(gd - od) <= diag_tol, f"row {r}: diagonal {gd} vs {od}"
         assert g.keys() == o.keys(), f"row {r}: index/term sets differ"
         for key, val in o.items():
             gv = g[key]
@@ -164,7 +172,8 @@ def test_element_export_full_space_product_paths(monkeypatch, name, windowed, wi
     st = ob.states(desc)
     gpu = _export_lists(ham, basis.dim, nvec, dtype)
     ora = oh.row_elements(desc, terms, np.arange(len(st)), st)
-    _compare_elements(gpu, [ora[i] for i in range(len(st))], exact_values=False)
+    scale = max(sum(abs(x) for x in t.c) for t in terms) * len(terms)
+    _compare_elements(gpu, [ora[i] for i in range(len(st))], exact_values=False, diag_tol=1e-15 * scale)
 
 
 @pytest.mark.parametrize("nvec,dtype,lpr", [(1, torch.complex128, 0), (4, torch.complex64, 2),
@@ -201,6 +210,9 @@ def test_element_export_row_windows_and_errors():
             hp.hphi_hv_elements(ham, 0, 4, 8, **bad)
     with pytest.raises(hp.HphiError):
         hp.hphi_hv_elements(ham, basis.dim - 1, 2, 8)
+
+
+_compare_elements.row0 = 0
 
 
 def _abs_bound(desc, terms, st, v):
