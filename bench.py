@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--gate-steps", type=int, default=2000,
                     help="kh_honeycomb24: length of the complex64-vs-FP64 trajectory compared outside the timed "
                          "region (the configured 2000 TPQ steps; 0 skips it)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="kagome36: only time the FP32 and FP64 products of the start vector (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 1 GiB device copies (reference kernel for the PMC byte counters) and exit")
     ap.add_argument("--schedule", default="",
@@ -245,9 +247,12 @@ def run_headline(args, hp, torch, np):
         sched_1 = hp.hphi_hv_tune(ham, psi_1)
     torch.cuda.empty_cache()
 
-    # ---- batched mixed-precision TPQ (headline), then the plain FP64 single-vector path
-    ms_b, st_b = run_tpq_graph(hp, ham, psi_b, args.steps, args.warmup, l, torch)
-    ms_1, st_1 = run_tpq_graph(hp, ham, psi_1, args.steps, args.warmup, l, torch)
+    # ---- batched mixed-precision TPQ (headline), then the plain FP64 single-vector path: K timed
+    # steps, one hphi_tpq_step call each; the same K steps as one graph-replayed hphi_tpq_run call
+    # (its set-up included) are reported beside them
+    ms_b, st_b = run_tpq_steps(hp, ham, psi_b, args.steps, args.warmup, l, torch)
+    ms_1, st_1 = run_tpq_steps(hp, ham, psi_1, args.steps, args.warmup, l, torch)
+    ms_bg, _ = run_tpq_graph(hp, ham, psi_b, args.steps, args.warmup, l, torch)
 
     # ---- dominant kernel alone: the batched product exactly as a step calls it (a, b, input scale,
     # reductions), HIP events on the stream it runs on; and one eager step per call for comparison
@@ -286,7 +291,9 @@ def run_headline(args, hp, torch, np):
         "config": {"workload": "kh_honeycomb24_tpq_b16_c64", "model": "Kitaev-Heisenberg honeycomb",
                    "n_sites": ns, "dim": dim, "nvec": nvec, "K": -1.0, "J": 0.1, "tpq_l": l,
                    "storage": "complex64", "reductions": "fp64",
-                   "timed_call": "hphi_tpq_run: K steps, graph-replayed after the first"},
+                   "timed_call": "hphi_tpq_step, one call per step"},
+        "graph_run": {"ms_per_step": ms_bg, "call": "hphi_tpq_run over the same K steps (graph instantiation "
+                                                      "and the first, eager step included)"},
         "hbm_gbps_step": alg_bytes / (ms_b * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched_b),
@@ -306,6 +313,14 @@ def run_headline(args, hp, torch, np):
         v_host = psi_b.cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(w, w.terms, v_host, dim, nvec)
     print(json.dumps(res), flush=True)
+
+
+def run_tpq_steps(hp, ham, psi, steps, warmup, l, torch):
+    """W untimed steps, then exactly K timed hphi_tpq_step calls; returns (ms per timed step,
+    (buffer holding the state, the other buffer, its scale))."""
+    ms, a, scale, _, _ = run_tpq(hp, ham, psi.clone(), steps, warmup, l, torch)
+    b = torch.empty_like(a)
+    return ms, (a, b, scale)
 
 
 def run_tpq_graph(hp, ham, psi, steps, warmup, l, torch):
@@ -371,13 +386,21 @@ def energy_gate(hp, ham, psi_b, l, ns, n_steps, torch, np, chunk=500):
     du = np.abs(lo[:, 0, :] - hi[:, 0, :])
     rel = du / np.abs(hi[:, 0, :])
     worst = np.unravel_index(np.argmax(rel), rel.shape)
+    # near infinite temperature u_k passes through zero, where a relative error is not defined: the
+    # gate reads |du/u| over the steps with |u_k| >= 0.01 (0.02 of the energy range), and the
+    # absolute error over all steps is reported beside it
+    sel = np.abs(hi[:, 0, :]) >= 1e-2
+    rel_sel = float(rel[sel].max()) if sel.any() else float("nan")
     drel_beta = np.abs(lo[1:, 2, :] - hi[1:, 2, :]) / np.abs(hi[1:, 2, :])
     return {"steps": n_steps, "samples": nvec, "reference": "complex128 FP64 path from the same psi_0",
-            "max_rel_err": float(rel.max()), "max_rel_err_at": {"step": int(worst[0]), "sample": int(worst[1])},
+            "max_rel_err": float(rel.max()), "max_rel_err_at": {"step": int(worst[0]), "sample": int(worst[1]),
+                                                                "u": float(hi[worst[0], 0, worst[1]])},
+            "max_rel_err_where_abs_u_ge_0.01": rel_sel, "steps_with_abs_u_below_0.01": int((~sel).sum()),
             "max_abs_err": float(du.max()), "final_rel_err": float(rel[-1].max()),
             "final_u": [float(x) for x in hi[-1, 0, :4]], "final_beta": float(hi[-1, 2, :].mean()),
             "beta_max_rel_err": float(drel_beta.max()), "fp64_reevaluation": strict,
-            "gate": 1e-8, "passed": bool(rel.max() <= 1e-8), "seconds": time.perf_counter() - t0}
+            "gate": 1e-8, "passed": bool(rel_sel <= 1e-8 and max(x["max_rel_err"] for x in strict) <= 1e-8),
+            "seconds": time.perf_counter() - t0}
 
 
 def copy_reference(torch, nbytes=2 << 30, reps=5):
@@ -677,12 +700,27 @@ def run_kagome36(args, hp, torch, np):
     from oracle import c_oracle
     w = workload("kagome36_sz0")
     n_iter = args.steps
+    os.environ.setdefault("HPHI_PROGRESS", "10")     # the library reports every 10 Lanczos steps on stderr
     basis = hp.hphi_basis_build(w.basis)
     ham = hp.hphi_ham_build(basis, w.terms)
     dim = basis.dim
     g = torch.Generator(device="cuda")
     g.manual_seed(w.seeds[0])
     v0 = torch.empty(dim, dtype=torch.float32, device="cuda").normal_(generator=g)   # 36.3 GB
+    if args.kernel_only:
+        prod = {}
+        for label, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            x = v0 if dt == torch.float32 else v0.to(dt)
+            u = torch.empty_like(x)
+            hp.hphi_hv(ham, x, u)
+            torch.cuda.synchronize()
+            k_ms = _events_ms(lambda: hp.hphi_hv(ham, x, u), 2, torch)
+            prod[label] = {"product_ms": k_ms, "gbps": dim * x.element_size() * 2 / (k_ms * 1e-3) / 1e9}
+            print(f"[kagome36] {label} product {k_ms:.1f} ms", file=sys.stderr, flush=True)
+            del x, u
+            torch.cuda.empty_cache()
+        print(json.dumps({"workload": "kagome36_sz0_products", "dim": dim, "products": prod}), flush=True)
+        return
     out = {}
     for label, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
         if dt == torch.float64:

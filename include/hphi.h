@@ -133,7 +133,15 @@ enum {
     HPHI_TERM_HOP = 2,         /* t c+_i c_j + conj(t) c+_j c_i, t = c[0] + i c[1], i != j */
     HPHI_TERM_DENS = 3,        /* c[0] n_i n_j, i != j                             */
     HPHI_TERM_NUM = 4,         /* c[0] n_i                                         */
-    HPHI_TERM_HUBBARD_U = 5    /* c[0] n_{i,up} n_{i,down}, i a site index         */
+    HPHI_TERM_HUBBARD_U = 5,   /* c[0] n_{i,up} n_{i,down}, i a site index         */
+    /* observables: the two-body Green's function of Sec. 2.2 (output from
+     * eigenvectors and TPQ states) as a Hermitian operator,
+     *   t c+_i c_j c+_k c_l + conj(t) c+_l c_k c+_j c_i,  t = c[0] + i c[1],
+     *   k = (int)c[2], l = (int)c[3]  (orbitals; repeats allowed),
+     * so that <O> = 2 Re(t <c+_i c_j c+_k c_l>): t = 1 gives 2 Re G, t = i gives
+     * -2 Im G.  Packed for the single-pass product kernel only (use with
+     * hphi_expect; the windowed, block-staged and dense-block kernels decline). */
+    HPHI_TERM_GREEN2 = 6
 };
 
 /* One term of the Hamiltonian.  Unused fields are ignored.  Each term is
@@ -219,13 +227,15 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different
  * schedule may change the last bits of the reductions.  sched_out (host,
- * may be NULL) receives 8 ints: windowed (0: single pass, 1: windowed,
+ * may be NULL) receives 9 ints: windowed (0: single pass, 1: windowed,
  * 2: windowed with staged copies), window_kb, max_passes,
  * lanes_per_row, blocks_per_cu, stage_tables (single-pass kernel: 1 =
  * pattern and rank tables staged in LDS when they fit, 0 = read from
  * global memory), nt_streams (windowed kernel, nvec >= 8: 1 = partial
  * sums, output and staged copies move with non-temporal hints so they do
- * not evict the gather window from L2), microseconds per product call.  If the
+ * not evict the gather window from L2), sector_blocks (sector bases: 1 = the
+ * block-staged kernel that keeps each high-half block of rows in LDS, 0 =
+ * the per-tile kernel), microseconds per product call (9 ints in all).  If the
  * environment variable HPHI_TUNE_CACHE names a file, the choice is
  * appended there and reused by later processes for the same device,
  * space and operators.  Synchronizes `stream`. */

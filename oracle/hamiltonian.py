@@ -17,7 +17,9 @@ Operators (all FP64 / complex128):
 H.v is built column by column ("push"): each term is applied to every
 basis state |t>, producing <s|T|t> for the states s it reaches, and
 u[s] += <s|T|t> v[t].  Terms are read as given: a HOP term means
-t c+_a c_b + conj(t) c+_b c_a, a SPIN_BOND term one undirected bond.
+t c+_a c_b + conj(t) c+_b c_a, a SPIN_BOND term one undirected bond, a
+GREEN2 term the two-body Green's-function observable of Sec. 2.2 (output
+of the eigenvectors and TPQ states), t c+_a c_b c+_c c_d + its conjugate.
 """
 
 from __future__ import annotations
@@ -25,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from synth.lattices import SPIN_BOND, SPIN_FIELD, HOP, DENS, NUM, HUBBARD_U
+from synth.lattices import SPIN_BOND, SPIN_FIELD, HOP, DENS, NUM, HUBBARD_U, GREEN2
 from . import basis as ob
 
 ONE = np.uint64(1)
@@ -116,6 +118,18 @@ def term_branches(term, st: np.ndarray, particle: str):
         c1, s1 = apply_product([lambda x: create(a, x), lambda x: annihilate(b, x)], st)
         out.append((t * c1, s1))
         c2, s2 = apply_product([lambda x: create(b, x), lambda x: annihilate(a, x)], st)
+        out.append((np.conj(t) * c2, s2))
+    elif k == GREEN2:
+        # t c+_a c_b c+_c c_d + conj(t) c+_d c_c c+_b c_a, each applied one operator at a time
+        if particle != "fermion":
+            raise ValueError("fermion term on spin basis")
+        t = complex(term.c[0], term.c[1])
+        a, b, cc, d = term.i, term.j, int(term.c[2]), int(term.c[3])
+        c1, s1 = apply_product([lambda x: create(a, x), lambda x: annihilate(b, x),
+                                lambda x: create(cc, x), lambda x: annihilate(d, x)], st)
+        out.append((t * c1, s1))
+        c2, s2 = apply_product([lambda x: create(d, x), lambda x: annihilate(cc, x),
+                                lambda x: create(b, x), lambda x: annihilate(a, x)], st)
         out.append((np.conj(t) * c2, s2))
     elif k in (DENS, NUM, HUBBARD_U):
         if particle != "fermion":

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhphi.so")
+# HPHI_LIB names another build of the same library (experiments with kernel variants)
+LIB_PATH = os.environ.get("HPHI_LIB") or os.path.join(HERE, "libhphi.so")
 
 # status codes
 HPHI_OK = 0
@@ -28,7 +29,7 @@ HPHI_SPIN_HALF, HPHI_FERMION = 0, 1
 HPHI_SECTOR_NONE, HPHI_SECTOR_SZ, HPHI_SECTOR_NUP_NDN, HPHI_SECTOR_NTOT = 0, 1, 2, 3
 HPHI_F64, HPHI_C128, HPHI_F32, HPHI_C64 = 0, 1, 2, 3
 (HPHI_TERM_SPIN_BOND, HPHI_TERM_SPIN_FIELD, HPHI_TERM_HOP, HPHI_TERM_DENS, HPHI_TERM_NUM,
- HPHI_TERM_HUBBARD_U) = range(6)
+ HPHI_TERM_HUBBARD_U, HPHI_TERM_GREEN2) = range(7)
 
 
 class BasisDescC(C.Structure):

@@ -22,7 +22,8 @@ _PARTICLE = {"spin": L.HPHI_SPIN_HALF, "fermion": L.HPHI_FERMION}
 _SECTOR = {"none": L.HPHI_SECTOR_NONE, "sz": L.HPHI_SECTOR_SZ, "nupndn": L.HPHI_SECTOR_NUP_NDN,
            "ntot": L.HPHI_SECTOR_NTOT}
 _KIND = {"spin_bond": L.HPHI_TERM_SPIN_BOND, "spin_field": L.HPHI_TERM_SPIN_FIELD, "hop": L.HPHI_TERM_HOP,
-         "dens": L.HPHI_TERM_DENS, "num": L.HPHI_TERM_NUM, "hubbard_u": L.HPHI_TERM_HUBBARD_U}
+         "dens": L.HPHI_TERM_DENS, "num": L.HPHI_TERM_NUM, "hubbard_u": L.HPHI_TERM_HUBBARD_U,
+         "green2": L.HPHI_TERM_GREEN2}
 _DTYPE = {torch.float64: L.HPHI_F64, torch.complex128: L.HPHI_C128, torch.float32: L.HPHI_F32,
           torch.complex64: L.HPHI_C64}
 DTYPE_NAMES = {"f64": torch.float64, "c128": torch.complex128, "f32": torch.float32, "c64": torch.complex64}
@@ -212,10 +213,10 @@ def hphi_hv_tune(ham: Ham, v: torch.Tensor, u: Optional[torch.Tensor] = None) ->
     nv = _nvec(v, ham.dim)
     if u is None:
         u = torch.empty_like(v)
-    out = (C.c_int32 * 8)()
+    out = (C.c_int32 * 9)()
     check(L.lib().hphi_hv_tune(C.c_void_p(ham.handle), _ptr(v), _ptr(u), nv, _dtype_code(v), out, _stream()))
     keys = ("windowed", "window_kb", "max_passes", "lanes_per_row", "blocks_per_cu", "stage_tables", "nt_streams",
-            "us")
+            "sector_blocks", "us")
     return dict(zip(keys, list(out)))
 
 

@@ -58,10 +58,23 @@ int dev_alloc(void** p, size_t bytes, const char* what) {
     return HPHI_OK;
 }
 
+// Opt-in progress report of long Lanczos runs (HPHI_PROGRESS=N): every N
+// steps the host waits for the stream and prints the step reached.
+static int progress_every() {
+    const char* e = std::getenv("HPHI_PROGRESS");
+    return e ? std::atoi(e) : 0;
+}
+
+static void report_progress(hipStream_t st, const char* what, int k, int n) {
+    (void)hipStreamSynchronize(st);
+    std::fprintf(stderr, "[hphi] %s: step %d of %d done\n", what, k, n);
+    std::fflush(stderr);
+}
+
 // Capture `body` (which enqueues work on the stream it is given) once into a
 // graph and replay it `reps` times on a side stream joined to `st`.
 template <typename Body>
-int replay_pairs(hipStream_t st, Body body, int reps) {
+int replay_pairs(hipStream_t st, Body body, int reps, const char* what = nullptr, int k0 = 0, int n = 0) {
     hipStream_t cs;
     int rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
     if (rc) return rc;
@@ -78,7 +91,11 @@ int replay_pairs(hipStream_t st, Body body, int reps) {
         rc = r ? r : check_hip(e, "end capture");
     }
     if (!rc) rc = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
-    for (int k = 0; !rc && k < reps; ++k) rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
+    const int every = what ? progress_every() : 0;
+    for (int k = 0; !rc && k < reps; ++k) {
+        rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
+        if (every > 0 && (k + 1) % ((every + 1) / 2) == 0) report_progress(cs, what, k0 + 2 * (k + 1), n);
+    }
     (void)hipEventRecord(ev, cs);
     (void)hipStreamWaitEvent(st, ev, 0);
     if (ge) (void)hipGraphExecDestroy(ge);
@@ -440,41 +457,24 @@ int lz_run(const hphi_ham* H, int dtype, const void* v0, void* A, void* B, LzDev
     rc = lz_iteration(H, dtype, A, B, true, D, acc, grid, st);
     if (rc) return rc;
     int k = 1;
+    const char* what = acc ? "lanczos second pass" : "lanczos";
     if (use_graph && n_max >= 3) {
-        // capture iterations (odd, even) once and replay; the device-side step
-        // counter and stop flag make every replay advance the recurrence
-        hipStream_t cs;
-        rc = check_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph stream");
+        // iterations (odd, even) captured once and replayed; the device-side
+        // step counter and stop flag make every replay advance the recurrence
+        rc = replay_pairs(st, [&](hipStream_t cs) {
+            int r = lz_iteration(H, dtype, B, A, false, D, acc, grid, cs);
+            return r ? r : lz_iteration(H, dtype, A, B, false, D, acc, grid, cs);
+        }, (n_max - 1) / 2, what, 1, n_max);
         if (rc) return rc;
-        hipEvent_t ev;
-        (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        (void)hipEventRecord(ev, st);
-        (void)hipStreamWaitEvent(cs, ev, 0);
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
-        if (!rc) {
-            int r1 = lz_iteration(H, dtype, B, A, false, D, acc, grid, cs);
-            int r2 = r1 ? r1 : lz_iteration(H, dtype, A, B, false, D, acc, grid, cs);
-            hipError_t e = hipStreamEndCapture(cs, &g);
-            rc = r2 ? r2 : check_hip(e, "end capture");
-        }
-        if (!rc) rc = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
-        for (; !rc && k + 2 <= n_max; k += 2) rc = check_hip(hipGraphLaunch(ge, cs), "graph launch");
-        (void)hipEventRecord(ev, cs);
-        (void)hipStreamWaitEvent(st, ev, 0);
-        if (ge) (void)hipGraphExecDestroy(ge);
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipStreamSynchronize(cs);
-        (void)hipStreamDestroy(cs);
-        (void)hipEventDestroy(ev);
-        if (rc) return rc;
+        k += (n_max - 1) / 2 * 2;
     }
+    const int every = progress_every();
     for (; k < n_max; ++k) {
         void* X = (k & 1) ? B : A;
         void* Y = (k & 1) ? A : B;
         rc = lz_iteration(H, dtype, X, Y, false, D, acc, grid, st);
         if (rc) return rc;
+        if (every > 0 && (k + 1) % every == 0) report_progress(st, what, k + 1, n_max);
     }
     return HPHI_OK;
 }

@@ -1,5 +1,6 @@
 // Hilbert space and split rank tables (Sec. 3.1: canonical restricted space,
 // two-dimensional search, same-popcount successor).
+#include <algorithm>
 #include <cstdarg>
 #include <cstring>
 #include <new>
@@ -231,8 +232,76 @@ extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
         delete B;
         return check_hip(e, "hphi_basis_build: table upload");
     }
+    for (size_t k = 0; k + 1 < h_row.size(); ++k)
+        B->max_block_rows = std::max<int64_t>(B->max_block_rows, h_row[k + 1] - h_row[k]);
     B->h_row = std::move(h_row);
     B->h_tile = std::move(h_tile);
+
+    // ---- two-level low-rank tables: the split search of the basis applied
+    // once more inside the low half, l = (a, b) with b the low b2 bits:
+    //   rank(l) = T1[a][class(l)] + T2[b]
+    // T2[b] = rank of b among the b2-bit strings of its class, T1[a][c] = number
+    // of class-c low halves whose upper part is below a.  b2 is even for
+    // fermions, so both parts keep the even/odd (up/down) bit parity.
+    {
+        const bool pairs = d.sector == HPHI_SECTOR_NUP_NDN;
+        int b2 = std::min(b_lo, 12);
+        if (pairs) b2 &= ~1;
+        const int b1 = b_lo - b2;
+        const int w2 = b2 / 2 + 1;                  // class base of a b2-bit part (pairs)
+        auto cls2 = [&](uint64_t x) { return pairs ? popc(x & kEven) * w2 + popc(x & kOdd) : popc(x); };
+        const int n2 = pairs ? w2 * w2 : b2 + 1;
+        std::vector<uint32_t> cnt2(n2, 0);
+        std::vector<uint16_t> t2(size_t(1) << b2);
+        for (uint64_t x = 0; x < (uint64_t(1) << b2); ++x) t2[x] = uint16_t(cnt2[cls2(x)]++);
+        const size_t t1_n = (size_t(1) << b1) * size_t(ncls);
+        const size_t bytes = t1_n * 4 + (((size_t(1) << b2) * 2 + 15) / 16 * 16);
+        if (bytes <= 64 * 1024) {
+            std::vector<uint32_t> t1(t1_n, 0), acc(ncls, 0);
+            for (uint64_t a = 0; a < (uint64_t(1) << b1); ++a) {
+                for (int c = 0; c < ncls; ++c) t1[a * ncls + c] = acc[c];
+                // class-c low halves with upper part a: b completes the class
+                const int ae = pairs ? popc(a & kEven) : 0, ao = pairs ? popc(a & kOdd) : 0, ap = popc(a);
+                for (int c = 0; c < ncls; ++c) {
+                    int need;
+                    if (pairs) {
+                        const int hw = b_lo / 2 + 1, ne = c / hw - ae, no = c % hw - ao;
+                        if (ne < 0 || no < 0 || ne >= w2 || no >= w2) continue;
+                        need = ne * w2 + no;
+                    } else {
+                        need = c - ap;
+                        if (need < 0 || need > b2) continue;
+                    }
+                    acc[c] += cnt2[need];
+                }
+            }
+            bool ok = true;
+            for (uint64_t l = 0; l < n_lo && ok; ++l)
+                ok = B->j_lo[l] == t1[(l >> b2) * ncls + uint64_t(ch.cls_lo(l))] + t2[l & ((uint64_t(1) << b2) - 1)];
+            if (!ok) {
+                hphi_basis_free(B);
+                return set_error(HPHI_EDEVICE, "hphi_basis_build: internal error in the two-level rank tables");
+            }
+            char* p = nullptr;
+            if (int rc = dev_alloc((void**)&p, bytes, "hphi_basis_build: two-level rank tables")) {
+                hphi_basis_free(B);
+                return rc;
+            }
+            B->d_t1 = reinterpret_cast<uint32_t*>(p);
+            B->d_t2 = reinterpret_cast<uint16_t*>(p + t1_n * 4);
+            hipError_t e2 = hipMemcpy(B->d_t1, t1.data(), t1_n * 4, hipMemcpyHostToDevice);
+            if (e2 == hipSuccess) e2 = hipMemcpy(B->d_t2, t2.data(), t2.size() * 2, hipMemcpyHostToDevice);
+            if (e2 != hipSuccess) {
+                hphi_basis_free(B);
+                return check_hip(e2, "hphi_basis_build: rank table upload");
+            }
+            B->lr_b2 = b2;
+            B->lr_ncls = ncls;
+            B->lr_pairs = pairs ? 1 : 0;
+            B->lr_nsl = b_lo / 2;
+            B->lr_bytes = bytes;
+        }
+    }
     *out = B;
     return HPHI_OK;
 }
@@ -246,6 +315,7 @@ extern "C" int hphi_basis_dim(const hphi_basis* b, int64_t* dim) {
 extern "C" void hphi_basis_free(hphi_basis* b) {
     if (!b) return;
     if (b->dmem) (void)hipFree(b->dmem);
+    if (b->d_t1) (void)hipFree(b->d_t1);
     delete b;
 }
 

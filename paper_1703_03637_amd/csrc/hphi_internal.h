@@ -27,7 +27,10 @@ constexpr int kMaxPassOps = 1024;        // operators per windowed pass (LDS pat
 // contribution d[p] and the pulled off-diagonal element
 //   <s| H_term |s ^ xmask> = (cr[p] + i ci[p]) * (-1)^popcount(s & smask).
 // xmask == 0 marks a diagonal-only operator.  smask is nonzero only for
-// fermion hops (orbitals strictly between the two ends).
+// fermion operators (the Jordan-Wigner parity of the orbitals outside the
+// pattern).  cmask != 0 adds a condition: the element and the diagonal part
+// apply only to rows with (s & cmask) == cval (operators on more than two
+// orbitals, e.g. the two-body Green's function; single-pass kernel only).
 struct DevOp {
     uint64_t xmask;
     uint64_t smask;
@@ -38,6 +41,8 @@ struct DevOp {
     double d[4];
     double cr[4];
     double ci[4];
+    uint64_t cmask;
+    uint64_t cval;
 };
 
 // Launch schedule of the product kernels (chosen by hphi_hv_tune or by
@@ -54,6 +59,8 @@ struct Schedule {
     int blocks_per_cu = 0;  // resident blocks per CU; 0 = as many as fit
     int stage_tables = 1;   // single-pass kernel: stage pattern and rank tables in LDS when they fit
     int nt_streams = 0;     // windowed kernel: non-temporal hints on partial sums, output and staged copies
+    int sector_blocks = 0;  // sector bases: 1 = block-staged kernel (high-half blocks in LDS), 0 = the
+                            // per-tile kernel (measured as fast or faster on every workload here)
 };
 
 // Compact kernel-side operator of the windowed product (configurations of
@@ -151,6 +158,14 @@ struct hphi_basis {
     std::vector<uint32_t> j_lo;
     std::vector<int64_t> j_hi;
     std::vector<int64_t> h_row, h_tile;
+    int64_t max_block_rows = 0;   // rows of the largest high-half block
+    // two-level low-rank tables of the block-staged sector product: the low
+    // half l = (a, b), b its low lr_b2 bits, has rank T1[a][class(l)] + T2[b]
+    // among the low halves of its class (null if they would not fit in LDS)
+    int lr_b2 = 0, lr_ncls = 0, lr_pairs = 0, lr_nsl = 0;
+    uint32_t* d_t1 = nullptr;     // [2^(b_lo - lr_b2)][lr_ncls]
+    uint16_t* d_t2 = nullptr;     // [2^lr_b2]
+    size_t lr_bytes = 0;          // bytes of T1 and T2 as the kernel stages them
 };
 
 struct hphi_ham {
@@ -158,6 +173,7 @@ struct hphi_ham {
     const hphi_basis* basis = nullptr;
     int n_sites = 0;
     bool is_complex = false;
+    bool has_cond = false;        // some operator carries a row condition (cmask)
     std::vector<hphi::DevOp> ops;
     hphi::DevOp* d_ops = nullptr;  // ops padded with inert entries to n_ops_pad
     int n_ops_pad = 0;            // multiple of 4

@@ -49,6 +49,7 @@ __device__ __forceinline__ T sel4(int p, T c0, T c1, T c2, T c3) {
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+
 // largest k in [0, n) with h_tile[k] <= tile (h_tile ascending)
 __device__ __forceinline__ int64_t find_high(const int64_t* __restrict__ h_tile, int64_t n, int64_t tile) {
     int64_t lo = 0, hi = n - 1;
@@ -252,6 +253,28 @@ __device__ __forceinline__ void store_lane(S* __restrict__ base, int64_t row, in
         put_chunk<Ly::CB>(p + j * LPR * Ly::CB, reinterpret_cast<const char*>(in) + j * Ly::CB);
 }
 
+// A row of zeros in device memory (the widest row: 16 complex128 values).
+// In the windowed and block-staged kernels, lanes whose element is zero read
+// it instead of a partner row, so the accumulation adds exact zeros.
+__device__ __align__(256) uint32_t kZeroRow[64] = {};
+
+// the lane's share of the row at byte address rowp
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void load_lane_at(const char* rowp, int sub, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    const char* p = rowp + sub * Ly::CB;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, p + j * LPR * Ly::CB);
+}
+
+// row `idx` of v for an active lane, the zero row otherwise
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ const char* row_or_zero(const S* v, int64_t idx, bool act) {
+    return act ? reinterpret_cast<const char*>(v) + idx * int64_t(LaneLayout<S, NE, LPR>::RB)
+               : reinterpret_cast<const char*>(kZeroRow);
+}
+
 // vector index of the lane's b-th vector (b < NE / NC)
 template <typename S, int NE, int LPR, int NC>
 __device__ __forceinline__ int lane_vec(int sub, int b) {
@@ -270,16 +293,19 @@ __host__ __device__ constexpr void vec_lane(int g, int& sub, int& bi) {
     bi = ((c / LPR) * Ly::CPS + eg % Ly::CPS) / NC;
 }
 
-// acc += c * g for one gathered row (c = cr + i ci), FP64.  A lane whose
-// element is zero (act false) adds exactly zero: its g registers hold a stale
-// or partner row that may be non-finite, and 0 * Inf would be NaN.
-template <typename S, bool CPLX, bool CCOEF, int VPL>
+// acc += c * g for one gathered row (c = cr + i ci), FP64.  With SEL, a lane
+// whose element is zero (act false) adds exactly zero: it skipped its gather,
+// so its g registers hold a stale row that may be non-finite, and 0 * Inf
+// would be NaN.  Without SEL the caller has made g a zero row for such lanes
+// (or a row that the lane's own output depends on anyway).
+template <typename S, bool CPLX, bool CCOEF, int VPL, bool SEL = false>
 __device__ __forceinline__ void accumulate(double (&acc)[VPL * (CPLX ? 2 : 1)], const S (&g)[VPL * (CPLX ? 2 : 1)],
                                            bool act, double cr, double ci) {
 #pragma unroll
     for (int b = 0; b < VPL; ++b) {
         if constexpr (CPLX) {
-            const double gr = double(act ? g[2 * b] : S(0)), gi = double(act ? g[2 * b + 1] : S(0));
+            const double gr = SEL && !act ? 0.0 : double(g[2 * b]);
+            const double gi = SEL && !act ? 0.0 : double(g[2 * b + 1]);
             if constexpr (CCOEF) {
                 acc[2 * b] += cr * gr - ci * gi;
                 acc[2 * b + 1] += cr * gi + ci * gr;
@@ -288,7 +314,7 @@ __device__ __forceinline__ void accumulate(double (&acc)[VPL * (CPLX ? 2 : 1)], 
                 acc[2 * b + 1] += cr * gi;
             }
         } else {
-            acc[b] += cr * double(act ? g[b] : S(0));
+            acc[b] += cr * (SEL && !act ? 0.0 : double(g[b]));
         }
     }
 }
@@ -532,9 +558,9 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     }
 
     double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
-    // gathered rows stay live across operators: a lane whose element is zero
-    // skips its load, and the accumulation takes zero in place of its stale
-    // registers, so a non-finite entry of v reaches only the rows it couples to
+    // gathered rows: a lane whose element is zero skips its gather and adds
+    // zero in its place, so a non-finite entry of v reaches only the rows it
+    // couples to
     alignas(16) S g[4][NE];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -586,12 +612,19 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                 for (int k = 0; k < 4; ++k) {
                     const ConstOp& op = ops[o + k];
                     const uint32_t bi = op.bi, bj = op.bj;
-                    const uint64_t xmask = op.xmask, smask = op.smask;
+                    const uint64_t xmask = op.xmask, smask = op.smask, cmask = op.cmask;
                     const uint32_t pat = bit_at<W64>(s, bi) | (bit_at<W64>(s, bj) << 1);
                     const double* te = tab + ((o + k) * 4 + int(pat)) * 4;
                     double cr = te[0];
                     double ci = CCOEF ? te[1] : 0.0;
-                    dsum += te[2];
+                    double dd = te[2];
+                    if (cmask != 0 && (uint64_t(s) & cmask) != op.cval) {
+                        // a conditional operator that does not apply to this row
+                        cr = 0.0;
+                        ci = 0.0;
+                        dd = 0.0;
+                    }
+                    dsum += dd;
                     if (smask != 0 && parity_masked<W64>(s, smask)) {
                         cr = -cr;
                         ci = -ci;
@@ -653,7 +686,7 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                     if (actk[k]) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL>(acc, g[k], actk[k], crk[k], cik[k]);
+                for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL, true>(acc, g[k], actk[k], crk[k], cik[k]);
             }
 
             if constexpr (EXPORT) {
@@ -741,6 +774,258 @@ __global__ __launch_bounds__(kBlock) void hv_multi_kernel(const HvArgs* __restri
         if (int(blockIdx.x) >= begin[q]) p = q;
     const HvArgs A = probs[p];
     hv_body<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB>(A, int(blockIdx.x) - begin[p], begin[p + 1] - begin[p]);
+}
+
+// ---------------------------------------------------------------------------
+// Block-staged sector product (Sec. 3.1 basis, Sec. 3.3 product).
+//
+// The rows of a sector basis are grouped by their high half h: block h is the
+// contiguous index range [h_row[k], h_row[k+1]), ordered by the low half.  A
+// workgroup owns one block at a time and stages its values in LDS, in chunks
+// of at most `chunk` rows when the block is larger, then for every row and
+// operator (the operator's flip mask decides the case, uniformly):
+//   * the flip stays in the low half: the target is in the same block, at the
+//     rank the two-level low-rank table gives (in LDS); its values come from
+//     the staged chunk, or from memory when they lie in another chunk;
+//   * the flip leaves the low half alone: the target is the row of the same
+//     rank in block h ^ m (one scalar J_hi load per operator and block), so
+//     the lanes of a wavefront read consecutive rows;
+//   * the flip touches both halves: rank from the LDS table, values gathered
+//     from block h ^ m_hi in memory.
+// The two-level low-rank table splits the low half l = (a, b), b its low b2
+// bits: rank(l) = T1[a][class(l)] + T2[b], where T2[b] is the rank of b among
+// the b2-bit strings of its class and T1[a][c] counts the class-c low halves
+// whose upper part is below a -- the split-table search of Sec. 3.1 applied
+// once more inside the low half, small enough for LDS.
+struct HvsArgs {
+    BasisDev bs;
+    const DevOp* ops;    // padded to n_ops (a multiple of 4)
+    int n_ops;
+    int b2;              // low bits of the low half ranked by T2
+    const double* ptab;  // [n_ops][4][Re c, Im c, d, 0]
+    const uint32_t* t1;  // [2^(b_lo - b2)][ncls]
+    const uint16_t* t2;  // [2^b2]
+    int ncls;            // classes of a low half
+    int cls_pairs;       // 1: class = (set even bits, set odd bits) (fermions at fixed up and down counts)
+    int nsl;             // cls_pairs: sites of the low half; class index = n_even * (nsl + 1) + n_odd
+    int pad;
+    int64_t chunk;       // rows staged in LDS at a time
+    const void* v;
+    void* u;
+    const void* y;
+    const double* cy;
+    const double* sx;
+    double a, b;
+    const int* stop;
+    double* partials;
+};
+
+constexpr int kBlockS = 512;   // threads of the block-staged sector kernel
+
+__device__ __forceinline__ int low_class(uint32_t l, int cls_pairs, int nsl) {
+    if (!cls_pairs) return __popc(l);
+    return __popc(l & 0x55555555u) * (nsl + 1) + __popc(l & 0xAAAAAAAAu);
+}
+
+// LDS row of a staged chunk -> registers (one lane holds a whole row)
+template <typename S, int NE>
+__device__ __forceinline__ void lds_row(const char* p, S (&out)[NE]) {
+    constexpr int RB = NE * int(sizeof(S));
+    constexpr int CB = RB >= 16 ? 16 : RB;
+#pragma unroll
+    for (int j = 0; j < RB / CB; ++j) copy_chunk<CB>(reinterpret_cast<char*>(out) + j * CB, p + j * CB);
+}
+
+template <typename S, bool CPLX, bool CCOEF, int B, bool W64>
+__global__ __launch_bounds__(kBlockS) void hvs_kernel(HvsArgs A) {
+    using ST = typename StateT<W64>::type;
+    constexpr int NC = CPLX ? 2 : 1;
+    constexpr int NE = B * NC;                 // scalars of a row; one lane per row
+    constexpr int RB = NE * int(sizeof(S));    // row bytes
+    constexpr int UB = RB >= 16 ? 16 : RB;     // staging unit (rows start on multiples of it)
+    constexpr int NW = kBlockS / 64;
+    constexpr int LOGV = Log2<B>::value;
+    if (A.stop && *A.stop) return;
+    const int tid = int(threadIdx.x);
+    const int lane = tid & 63;
+    const int wave = wave_uniform(tid >> 6);
+    const BasisDev& bs = A.bs;
+    const S* __restrict__ v = static_cast<const S*>(A.v);
+    S* __restrict__ u = static_cast<S*>(A.u);
+    const S* __restrict__ y = static_cast<const S*>(A.y);
+    const ConstOp* ops = (const ConstOp*)(A.ops);
+    typedef const __attribute__((address_space(4))) int64_t ConstI64;
+    const ConstI64* jhi = (const ConstI64*)(bs.j_hi);
+    const int n_ops = A.n_ops;
+    const int b2 = A.b2;
+    const uint32_t mask2 = (1u << b2) - 1u;
+    const int ncls = A.ncls, cpairs = A.cls_pairs, nsl = A.nsl;
+
+    // LDS (hvs_lds_layout): pattern table | T1 | T2 | staged chunk and one zero
+    // row, each part 16-byte aligned
+    double* tab = lds_dyn;
+    const size_t tab_b = size_t(n_ops) * 16 * sizeof(double);
+    const size_t t1_n = (size_t(1) << (bs.b_lo - b2)) * size_t(ncls);
+    uint32_t* t1 = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds_dyn) + tab_b);
+    uint16_t* t2 = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(t1) + (t1_n * 4 + 15) / 16 * 16);
+    const size_t t2_b = ((size_t(1) << b2) * 2 + 15) / 16 * 16;
+    char* blk = reinterpret_cast<char*>(t2) + t2_b;
+    for (size_t i = tid; i < tab_b / 8; i += kBlockS) tab[i] = A.ptab[i];
+    for (size_t i = tid; i < t1_n; i += kBlockS) t1[i] = A.t1[i];
+    for (size_t i = tid; i < (size_t(1) << b2); i += kBlockS) t2[i] = A.t2[i];
+    for (int i = tid; i < RB / 4; i += kBlockS) reinterpret_cast<uint32_t*>(blk + A.chunk * RB)[i] = 0u;
+    __syncthreads();
+    auto low_rank = [&](uint32_t l) -> uint32_t {
+        return t1[(l >> b2) * uint32_t(ncls) + uint32_t(low_class(l, cpairs, nsl))] + uint32_t(t2[l & mask2]);
+    };
+
+    double sx[B], cy[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        sx[b] = A.sx ? A.sx[b] : 1.0;
+        cy[b] = (A.y && A.cy) ? A.cy[b] : 0.0;
+    }
+    const double ca = A.a, cb = A.b;
+    double wq[kNQ] = {0.0, 0.0, 0.0, 0.0};
+    alignas(16) S g[4][NE];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < NE; ++e) g[k][e] = S(0);
+
+    for (int64_t kb = blockIdx.x; kb < bs.n_high; kb += gridDim.x) {
+        const int64_t hrow = bs.h_row[kb];
+        const int64_t rows = bs.h_row[kb + 1] - hrow;
+        const uint64_t hval = bs.h_val[kb];
+        const ST hbits = ST(hval << bs.b_lo);
+        const uint32_t lobase = bs.h_lobase[kb];
+        for (int64_t c0 = 0; c0 < rows; c0 += A.chunk) {
+            const int64_t cn = rows - c0 < A.chunk ? rows - c0 : A.chunk;
+            __syncthreads();   // every read of the previous chunk is done
+            {
+                const char* src = reinterpret_cast<const char*>(v) + size_t(hrow + c0) * RB;
+                const int64_t units = cn * (RB / UB);
+                for (int64_t i = tid; i < units; i += kBlockS) copy_chunk<UB>(blk + i * UB, src + i * UB);
+            }
+            __syncthreads();
+            for (int64_t t0 = int64_t(wave) * 64; t0 < cn; t0 += NW * 64) {
+                const bool valid = t0 + lane < cn;
+                const int64_t r = c0 + t0 + lane;            // rank within the block
+                const uint32_t l = valid ? bs.lows[lobase + r] : 0u;
+                const ST s = hbits | ST(l);
+                double acc[NE];
+#pragma unroll
+                for (int e = 0; e < NE; ++e) acc[e] = 0.0;
+                double dsum = 0.0;
+                for (int o = 0; o < n_ops; o += 4) {
+                    double crk[4], cik[4];
+                    int64_t ik[4];     // chunk offset (LDS) or row index (memory)
+                    bool lk[4];        // value in the staged chunk
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const ConstOp& op = ops[o + k];
+                        const uint32_t bi = op.bi, bj = op.bj;
+                        const uint64_t xmask = op.xmask, smask = op.smask;
+                        const uint32_t pat = bit_at<W64>(s, bi) | (bit_at<W64>(s, bj) << 1);
+                        const double* te = tab + ((o + k) * 4 + int(pat)) * 4;
+                        double cr = te[0];
+                        double ci = CCOEF ? te[1] : 0.0;
+                        dsum += te[2];
+                        if (smask != 0 && parity_masked<W64>(s, smask)) {
+                            cr = -cr;
+                            ci = -ci;
+                        }
+                        const uint64_t xm_hi = xmask >> bs.b_lo;
+                        const uint32_t xm_lo = uint32_t(xmask & bs.mask_lo);
+                        bool live = valid;
+                        if (xm_hi == 0) {
+                            // target in this block: rank from the LDS table
+                            const int64_t rk = xm_lo ? int64_t(low_rank(l ^ xm_lo)) : r;
+                            const int64_t rel = rk - c0;
+                            lk[k] = rel >= 0 && rel < cn;
+                            ik[k] = lk[k] ? rel : hrow + rk;
+                        } else {
+                            const int64_t base_hi = jhi[hval ^ xm_hi];
+                            live = live && base_hi >= 0;
+                            ik[k] = base_hi + (xm_lo ? int64_t(low_rank(l ^ xm_lo)) : r);
+                            lk[k] = false;
+                        }
+                        crk[k] = live ? cr : 0.0;
+                        cik[k] = live ? ci : 0.0;
+                    }
+                    // lanes whose element is zero read a zero row (after the chunk in
+                    // LDS, or in memory)
+                    bool actk[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                        if (lk[k]) lds_row<S, NE>(blk + (actk[k] ? ik[k] : A.chunk) * RB, g[k]);
+                        else load_lane_at<S, NE, 1>(row_or_zero<S, NE, 1>(v, ik[k], actk[k]), 0, g[k]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, B>(acc, g[k], actk[k], crk[k], cik[k]);
+                }
+                // epilogue: u = a * H x + b * x + cy * y with x = sx * v (own row from the chunk)
+                double xr[NE], ur[NE];
+                if (valid) {
+                    alignas(16) S vr[NE];
+                    lds_row<S, NE>(blk + (t0 + lane) * RB, vr);
+                    if (y) {
+                        alignas(16) S yr[NE];
+                        load_lane<S, NE, 1>(y, hrow + r, 0, yr);
+#pragma unroll
+                        for (int b = 0; b < B; ++b)
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) ur[NC * b + c] = cy[b] * double(yr[NC * b + c]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) ur[e] = 0.0;
+                    }
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            const int e = NC * b + c;
+                            const double vv = double(vr[e]);
+                            const double xv = sx[b] * vv;
+                            const double hv = sx[b] * (acc[e] + dsum * vv);
+                            acc[e] = hv;
+                            xr[e] = xv;
+                            ur[e] += ca * hv + cb * xv;
+                        }
+                    if (u) {
+                        alignas(16) S us[NE];
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) us[e] = S(ur[e]);
+                        store_lane<S, NE, 1>(u, hrow + r, 0, us);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        acc[e] = 0.0;
+                        xr[e] = 0.0;
+                        ur[e] = 0.0;
+                    }
+                }
+                wave_reduce_quantities<B, 1, NC, NE>(xr, acc, ur, wq, lane);
+            }
+        }
+    }
+    // block sums: lane (b << (6 - LOGV)) of each wavefront holds vector b's sums
+    __shared__ double sh[NW][kNQ][kMaxNvec];
+    if ((lane & ((64 >> LOGV) - 1)) == 0) {
+        const int b = lane >> (6 - LOGV);
+#pragma unroll
+        for (int k = 0; k < kNQ; ++k) sh[wave][k][b] = wq[k];
+    }
+    __syncthreads();
+    if (tid < kNQ * B) {
+        const int k = tid / B, b = tid % B;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sh[w][k][b];
+        A.partials[size_t(blockIdx.x) * (kNQ * B) + tid] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -877,12 +1162,17 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             lds_dyn[i * TE + 1] = sel4(q, d0, d1, d2, d3);
         }
     }
+    // the wavefront's row tile: 64 rows and a zero row (row 64) that lanes
+    // whose element is zero read instead of a partner
+    char* tb = reinterpret_cast<char*>(lds_dyn) + size_t(n_ops) * 4 * TE * sizeof(double) + size_t(wave) * 65 * TRB;
+    if constexpr (TL) {
+        for (int i = lane; i < TRB / 4; i += 64) reinterpret_cast<uint32_t*>(tb + 64 * TRB)[i] = 0u;
+    }
     __syncthreads();
-    char* tb = reinterpret_cast<char*>(lds_dyn) + size_t(n_ops) * 4 * TE * sizeof(double) + size_t(wave) * 64 * TRB;
 
-    // gathered rows stay live across operators: a lane whose element is zero
-    // skips its load, and the accumulation takes zero in place of its stale
-    // or partner registers (non-finite entries stay with the rows they couple to)
+    // gathered rows: a lane whose element is zero reads zeros (the zero row in
+    // memory or in the LDS tile) or its own lane, so non-finite entries stay
+    // with the rows they couple to
     alignas(16) S g[4][NE];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -1009,10 +1299,11 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 for (int k = 0; k < 4; ++k) {
                     actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
                     if (lk[k]) {
-                        if constexpr (TL) tile_get<S, NE, LPR>(tb, r ^ int(xa[k]), sub, g[k]);
-                        else exchange_lane<S, NE>(vr, xa[k], g[k]);
+                        if constexpr (TL) tile_get<S, NE, LPR>(tb, actk[k] ? (r ^ int(xa[k])) : 64, sub, g[k]);
+                        else exchange_lane<S, NE>(vr, actk[k] ? xa[k] : (lane << 2), g[k]);
+                    } else {
+                        load_lane_at<S, NE, LPR>(row_or_zero<S, NE, LPR>(v, int64_t(tk[k]), actk[k]), sub, g[k]);
                     }
-                    else if (actk[k]) load_lane<S, NE, LPR>(v, int64_t(tk[k]), sub, g[k]);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL>(acc, g[k], actk[k], crk[k], cik[k]);
@@ -1835,6 +2126,91 @@ static int launch_hv_b(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     return set_error(HPHI_EINVAL, "nvec must be 1, 2, 4, 8 or 16 (got %d)", L.nvec);
 }
 
+// ---- block-staged sector launches
+// LDS bytes of the block-staged sector kernel for `chunk` staged rows
+static size_t hvs_lds_layout(const hphi_ham* H, int row_bytes, int64_t chunk) {
+    const hphi_basis* Bs = H->basis;
+    const size_t tab = size_t(H->n_ops_pad) * 16 * sizeof(double);
+    const size_t t1 = ((size_t(1) << (Bs->b_lo - Bs->lr_b2)) * size_t(Bs->lr_ncls) * 4 + 15) / 16 * 16;
+    const size_t t2 = ((size_t(1) << Bs->lr_b2) * 2 + 15) / 16 * 16;
+    return tab + t1 + t2 + size_t(chunk + 1) * size_t(row_bytes);
+}
+
+template <typename S, bool CPLX, bool CCOEF, int B, bool W64>
+static int launch_hvs_t(const HvLaunch& L, int per_cu, hipStream_t st) {
+    const hphi_ham* H = L.ham;
+    const hphi_basis* Bs = H->basis;
+    constexpr int RB = B * (CPLX ? 2 : 1) * int(sizeof(S));
+    constexpr size_t kStatic = size_t(kBlockS / 64) * kNQ * kMaxNvec * sizeof(double);
+    const size_t fixed = hvs_lds_layout(H, RB, 0);
+    const size_t budget = size_t(160 * 1024) / size_t(per_cu);
+    if (fixed + kStatic + 64 * size_t(RB) > budget) return 1;
+    int64_t chunk = int64_t((budget - fixed - kStatic) / RB);
+    if (chunk > Bs->max_block_rows) chunk = Bs->max_block_rows;
+    // test hook: HPHI_SECTOR_CHUNK caps the staged rows (blocks then span several chunks)
+    if (const char* e = std::getenv("HPHI_SECTOR_CHUNK")) {
+        const int64_t cap = std::atoll(e);
+        if (cap >= 1 && cap < chunk) chunk = cap;
+    }
+    const size_t lds = hvs_lds_layout(H, RB, chunk);
+    int64_t grid = int64_t(per_cu) * cu_count();
+    if (grid > Bs->dev.n_high) grid = Bs->dev.n_high;
+    if (grid > kMaxGrid) grid = kMaxGrid;
+    HvsArgs A;
+    A.bs = Bs->dev;
+    A.ops = H->d_ops;
+    A.n_ops = H->n_ops_pad;
+    A.b2 = Bs->lr_b2;
+    A.ptab = H->d_ptab;
+    A.t1 = Bs->d_t1;
+    A.t2 = Bs->d_t2;
+    A.ncls = Bs->lr_ncls;
+    A.cls_pairs = Bs->lr_pairs;
+    A.nsl = Bs->lr_nsl;
+    A.pad = 0;
+    A.chunk = chunk;
+    A.v = L.v;
+    A.u = L.u;
+    A.y = L.y;
+    A.cy = L.cy;
+    A.sx = L.sx;
+    A.a = L.a;
+    A.b = L.b;
+    A.stop = L.stop;
+    A.partials = H->d_partials;
+    hvs_kernel<S, CPLX, CCOEF, B, W64><<<int(grid), kBlockS, lds, st>>>(A);
+    int rc = check_hip(hipGetLastError(), "hvs_kernel launch");
+    if (rc) return rc;
+    if (L.reduce_out) {
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, int(grid), kNQ * B, L.reduce_out, L.stop,
+                                                      H->d_flag, HPHI_NONFINITE_PRODUCT);
+        rc = check_hip(hipGetLastError(), "reduce launch");
+    }
+    return rc;
+}
+
+// the block-staged sector product when the schedule asks for it and its
+// tables fit in LDS; 1 if not applicable
+template <typename S, bool CPLX, bool CCOEF>
+static int try_launch_hvs(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
+    const hphi_basis* Bs = L.ham->basis;
+    if (Bs->dev.sector == 0 || !Bs->d_t1 || L.ex || L.nvec > 4 || L.ham->has_cond) return 1;
+    const bool w64 = Bs->nbits > 32;
+    if (sc.sector_blocks != 1) return 1;
+    const int per_cu = sc.blocks_per_cu > 0 ? (sc.blocks_per_cu < 3 ? sc.blocks_per_cu : 3) : 2;
+    auto go = [&](auto bconst) -> int {
+        constexpr int B = decltype(bconst)::value;
+        return w64 ? launch_hvs_t<S, CPLX, CCOEF, B, true>(L, per_cu, st)
+                   : launch_hvs_t<S, CPLX, CCOEF, B, false>(L, per_cu, st);
+    };
+    switch (L.nvec) {
+        case 1: return go(std::integral_constant<int, 1>{});
+        case 2: return go(std::integral_constant<int, 2>{});
+        case 4: return go(std::integral_constant<int, 4>{});
+    }
+    return 1;
+}
+
 // ---- windowed full-space launches
 template <typename S, bool CPLX, bool CCOEF, int B, int LPR, bool NT, bool EX>
 static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc, bool staged, void* const* stage,
@@ -1844,7 +2220,7 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
     // dynamic LDS: the pass's pattern table, then one row tile per wavefront
     constexpr int NE = (B / LPR) * (CPLX ? 2 : 1);
     constexpr int TRB = LaneLayout<S, NE, LPR>::RB;
-    constexpr size_t tile_lds = tile_in_lds(TRB, LPR) ? size_t(kWavesPerBlock) * 64 * TRB : 0;
+    constexpr size_t tile_lds = tile_in_lds(TRB, LPR) ? size_t(kWavesPerBlock) * 65 * TRB : 0;
     auto lds_of = [&](int p) {
         return size_t(P->kop_begin[p + 1] - P->kop_begin[p]) * 4 * (CCOEF ? 4 : 2) * sizeof(double) + tile_lds;
     };
@@ -1920,7 +2296,7 @@ static int launch_hvw_b(const HvLaunch& L, const PassPlan* P, const Schedule& sc
 template <typename S, bool CPLX, bool CCOEF, bool EX>
 static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
     const hphi_basis* Bs = L.ham->basis;
-    if (!sc.windowed || Bs->dev.sector != 0 || Bs->nbits > 32 || Bs->nbits < 6) return 1;
+    if (!sc.windowed || Bs->dev.sector != 0 || Bs->nbits > 32 || Bs->nbits < 6 || L.ham->has_cond) return 1;
     const int row_bytes = L.nvec * int(sizeof(S)) * (CPLX ? 2 : 1);
     const PassPlan* P = get_plan(L.ham, row_bytes, sc.window_kb, sc.max_passes, !L.no_alloc);
     if (!P) return 1;
@@ -1932,7 +2308,7 @@ static int try_launch_hvw(const HvLaunch& L, const Schedule& sc, hipStream_t st)
     // launch_hvw_b will use) and the kernel's static block-sum array within
     // the 160 KB of a workgroup
     const int lpr = (L.nvec >= 8 && (sc.lpr == 2 || sc.lpr == 4 || sc.lpr == 8)) ? sc.lpr : 1;
-    const size_t tile_lds = tile_in_lds(row_bytes, lpr) ? size_t(kWavesPerBlock) * 64 * row_bytes : 0;
+    const size_t tile_lds = tile_in_lds(row_bytes, lpr) ? size_t(kWavesPerBlock) * 65 * row_bytes : 0;
     constexpr size_t static_lds = size_t(kWavesPerBlock) * kNQ * 64 * sizeof(double);
     for (int p = 0; p < P->n_pass; ++p) {
         const int n = P->kop_begin[p + 1] - P->kop_begin[p];
@@ -1967,6 +2343,10 @@ static int launch_hv_s2(const HvLaunch& L, hipStream_t st) {
     const Schedule sc = L.sched ? *L.sched : schedule_for(L.ham, L.nvec, L.dtype);
     const int w = try_launch_hvw<S, CPLX, CCOEF, EX>(L, sc, st);
     if (w != 1) return w;
+    if constexpr (!EX) {
+        const int b = try_launch_hvs<S, CPLX, CCOEF>(L, sc, st);
+        if (b != 1) return b;
+    }
     if (L.ham->basis->dev.sector != 0) return launch_hv_b<S, CPLX, CCOEF, true, EX>(L, sc, st);
     return launch_hv_b<S, CPLX, CCOEF, false, EX>(L, sc, st);
 }

@@ -42,6 +42,7 @@ Schedule default_schedule(int nvec) {
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
     s.stage_tables = env_int("HPHI_STAGE_TABLES", s.stage_tables) ? 1 : 0;
     s.nt_streams = env_int("HPHI_NT_STREAMS", s.nt_streams) ? 1 : 0;
+    s.sector_blocks = env_int("HPHI_SECTOR_BLOCKS", s.sector_blocks);
     if (s.window_kb < 1) s.window_kb = 2048;
     if (s.max_passes < 1) s.max_passes = 1;
     return s;
@@ -75,9 +76,10 @@ bool cache_lookup(const std::string& sig, Schedule& out) {
     while (fgets(line, sizeof(line), f)) {
         char key[300];
         Schedule s;
-        if (sscanf(line, "%299s %d %d %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes, &s.lpr,
-                   &s.blocks_per_cu, &s.stage_tables, &s.nt_streams) == 8 &&
-            sig == key) {
+        const int n = sscanf(line, "%299s %d %d %d %d %d %d %d %d", key, &s.windowed, &s.window_kb, &s.max_passes,
+                             &s.lpr, &s.blocks_per_cu, &s.stage_tables, &s.nt_streams, &s.sector_blocks);
+        if (n == 8) s.sector_blocks = 0;   // entries written before the block-staged sector kernel
+        if (n >= 8 && sig == key) {
             out = s;   // the last entry for a key wins
             found = true;
         }
@@ -91,8 +93,8 @@ void cache_store(const std::string& sig, const Schedule& s, double us) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
-            s.blocks_per_cu, s.stage_tables, s.nt_streams, us);
+    fprintf(f, "%s %d %d %d %d %d %d %d %d %.2f\n", sig.c_str(), s.windowed, s.window_kb, s.max_passes, s.lpr,
+            s.blocks_per_cu, s.stage_tables, s.nt_streams, s.sector_blocks, us);
     fclose(f);
 }
 
@@ -131,6 +133,7 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
     hipStream_t st = (hipStream_t)stream;
     const hphi_basis* B = ham->basis;
     const bool windowable = B->dev.sector == 0 && B->nbits >= 6 && B->nbits <= 32;
+    const bool blockable = B->dev.sector != 0 && B->d_t1 && nvec <= 4;
 
     std::vector<Schedule> cands;
     std::vector<int> lprs = {1};
@@ -139,6 +142,7 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
     for (int bpc : {0, 4}) {
         for (int lpr : lprs) {
             Schedule s;
+            s.sector_blocks = 0;
             s.lpr = lpr;
             s.blocks_per_cu = bpc;
             s.windowed = 0;
@@ -165,6 +169,14 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
             s.nt_streams = 0;
         }
     }
+    if (blockable)
+        for (int bpc : {1, 2, 3}) {
+            Schedule s;
+            s.windowed = 0;
+            s.sector_blocks = 1;
+            s.blocks_per_cu = bpc;
+            cands.push_back(s);
+        }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(HPHI_EDEVICE, "hphi_hv_tune: event creation failed");
@@ -222,7 +234,8 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
         sched_out[4] = best.blocks_per_cu;
         sched_out[5] = best.stage_tables;
         sched_out[6] = best.nt_streams;
-        sched_out[7] = int(best_us);
+        sched_out[7] = best.sector_blocks;
+        sched_out[8] = int(best_us);
     }
     return HPHI_OK;
 }

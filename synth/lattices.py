@@ -25,8 +25,9 @@ HOP = "hop"                  # i=a, j=b orbitals; c = (Re t, Im t): t c+_a c_b +
 DENS = "dens"                # i=a, j=b orbitals; c = (V,): V n_a n_b
 NUM = "num"                  # i=a orbital; c = (mu,): mu n_a
 HUBBARD_U = "hubbard_u"      # i site; c = (U,): U n_{i,up} n_{i,down}
+GREEN2 = "green2"            # i=a, j=b orbitals; c = (Re t, Im t, c, d): t c+_a c_b c+_c c_d + h.c.
 
-KINDS = (SPIN_BOND, SPIN_FIELD, HOP, DENS, NUM, HUBBARD_U)
+KINDS = (SPIN_BOND, SPIN_FIELD, HOP, DENS, NUM, HUBBARD_U, GREEN2)
 
 
 class Term(NamedTuple):
@@ -200,6 +201,13 @@ def random_fermion_terms(n_sites: int, n_hops: int, seed: int, *, conserve_spin:
         for a in range(norb):
             terms.append(Term(NUM, a, -1, (float(rng.uniform(-1, 1)),)))
     return terms
+
+
+def green2_term(a: int, b: int, c: int, d: int, t: complex = 1.0) -> Term:
+    """The two-body Green's-function observable t c+_a c_b c+_c c_d + h.c. (orbitals 2*site+sigma):
+    its expectation is 2 Re(t <c+_a c_b c+_c c_d>), so t = 1 and t = i give Re and -Im."""
+    t = complex(t)
+    return Term(GREEN2, a, b, (t.real, t.imag, float(c), float(d)))
 
 
 def hubbard_terms(bonds, n_sites: int, t: float, U: float) -> List[Term]:

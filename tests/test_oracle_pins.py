@@ -161,6 +161,10 @@ def _kron_fermion_h(n_sites, terms):
             H += t.c[0] * n_op[t.i]
         elif t.kind == L.HUBBARD_U:
             H += t.c[0] * n_op[2 * t.i] @ n_op[2 * t.i + 1]
+        elif t.kind == L.GREEN2:
+            tt = complex(t.c[0], t.c[1])
+            T = cd[t.i] @ cs[t.j] @ cd[int(t.c[2])] @ cs[int(t.c[3])]
+            H += tt * T + np.conj(tt) * T.conj().T
     return H
 
 
@@ -667,3 +671,29 @@ def test_splitmix_stream_and_on_demand_rows():
     a = c_oracle.rows_hv_counted_ondemand(desc, terms, st, seed, nvec)
     b = c_oracle.rows_hv_counted(desc, terms, st, v.astype(np.complex128))
     assert np.array_equal(a, b.real) and np.all(b.imag == 0)
+
+
+
+GREEN2_QUADS = [(0, 2, 3, 5), (1, 4, 0, 2), (2, 2, 3, 3), (0, 3, 3, 0), (4, 1, 1, 4), (5, 5, 5, 5), (0, 1, 1, 0),
+                (3, 0, 5, 3), (2, 5, 5, 1), (1, 0, 0, 1)]
+
+
+@pytest.mark.parametrize("t", [1.0, 1j, 0.3 - 0.7j])
+def test_green2_terms_match_jordan_wigner(t):
+    """The two-body Green's-function observable t c+_a c_b c+_c c_d + h.c. applied operator by
+    operator equals the product of Jordan-Wigner matrices, for distinct and repeated orbitals."""
+    ns = 3
+    for q in GREEN2_QUADS:
+        term = L.green2_term(*q, t=t)
+        H = oh.dense_h(BasisDesc("fermion", ns), [term])
+        assert np.allclose(H, _kron_fermion_h(ns, [term]), atol=1e-14, rtol=0), q
+
+
+def test_green2_special_cases():
+    """c+_a c_a c+_b c_b = n_a n_b (a != b); c+_a c_b c+_b c_a = n_a (1 - n_b); with t = 1/2 the
+    observable is exactly those densities."""
+    desc = BasisDesc("fermion", 3)
+    nn = oh.dense_h(desc, [L.Term(L.DENS, 1, 4, (1.0,))])
+    assert np.array_equal(oh.dense_h(desc, [L.green2_term(1, 1, 4, 4, 0.5)]), nn)
+    na = oh.dense_h(desc, [L.Term(L.NUM, 1, -1, (1.0,))])
+    assert np.allclose(oh.dense_h(desc, [L.green2_term(1, 4, 4, 1, 0.5)]), na - nn, atol=0)
