@@ -300,6 +300,57 @@ extern "C" int hphi_basis_build(const hphi_basis_desc* desc, hphi_basis** out) {
             B->lr_pairs = pairs ? 1 : 0;
             B->lr_nsl = b_lo / 2;
             B->lr_bytes = bytes;
+
+            // compact 16-bit form for the single-pass kernel: T2p[b] packs the
+            // rank of b within its class (10 bits) with that class cb (6 bits),
+            // and T1c[a][cb] = T1[a][class(a) + cb], so that
+            //   rank(l) = T1c[a][T2p[b] >> 10] + (T2p[b] & 1023)
+            // needs no class arithmetic on the device
+            const uint32_t t1_max = *std::max_element(t1.begin(), t1.end());
+            if (t1_max < 65536 && n2 <= 64 && b2 <= 12) {
+                std::vector<uint16_t> t2p(size_t(1) << b2), t1c((size_t(1) << b1) * size_t(n2), 0);
+                for (uint64_t x = 0; x < (uint64_t(1) << b2); ++x)
+                    t2p[x] = uint16_t(uint32_t(t2[x]) | (uint32_t(cls2(x)) << 10));
+                const int hw = b_lo / 2 + 1;
+                for (uint64_t a = 0; a < (uint64_t(1) << b1); ++a)
+                    for (int cb = 0; cb < n2; ++cb) {
+                        int c;
+                        if (pairs) {
+                            const int ne = popc(a & kEven) + cb / w2, no = popc(a & kOdd) + cb % w2;
+                            if (ne >= hw || no >= hw) continue;
+                            c = ne * hw + no;
+                        } else {
+                            c = popc(a) + cb;
+                            if (c >= ncls) continue;
+                        }
+                        t1c[a * n2 + cb] = uint16_t(t1[a * ncls + c]);
+                    }
+                bool okc = true;
+                const uint64_t m2 = (uint64_t(1) << b2) - 1;
+                for (uint64_t l = 0; l < n_lo && okc; ++l) {
+                    const uint32_t p2 = t2p[l & m2];
+                    okc = B->j_lo[l] == uint32_t(t1c[(l >> b2) * n2 + (p2 >> 10)]) + (p2 & 1023u);
+                }
+                if (!okc) {
+                    hphi_basis_free(B);
+                    return set_error(HPHI_EDEVICE, "hphi_basis_build: internal error in the compact rank tables");
+                }
+                const size_t c1 = (t1c.size() * 2 + 15) / 16 * 16;
+                char* q = nullptr;
+                if (int rc = dev_alloc((void**)&q, c1 + t2p.size() * 2, "hphi_basis_build: compact rank tables")) {
+                    hphi_basis_free(B);
+                    return rc;
+                }
+                B->d_t1c = reinterpret_cast<uint16_t*>(q);
+                B->d_t2p = reinterpret_cast<uint16_t*>(q + c1);
+                hipError_t e3 = hipMemcpy(B->d_t1c, t1c.data(), t1c.size() * 2, hipMemcpyHostToDevice);
+                if (e3 == hipSuccess) e3 = hipMemcpy(B->d_t2p, t2p.data(), t2p.size() * 2, hipMemcpyHostToDevice);
+                if (e3 != hipSuccess) {
+                    hphi_basis_free(B);
+                    return check_hip(e3, "hphi_basis_build: compact rank table upload");
+                }
+                B->lr_n2 = n2;
+            }
         }
     }
     *out = B;
@@ -316,6 +367,7 @@ extern "C" void hphi_basis_free(hphi_basis* b) {
     if (!b) return;
     if (b->dmem) (void)hipFree(b->dmem);
     if (b->d_t1) (void)hipFree(b->d_t1);
+    if (b->d_t1c) (void)hipFree(b->d_t1c);
     delete b;
 }
 

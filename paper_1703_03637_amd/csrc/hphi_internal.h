@@ -58,6 +58,8 @@ struct Schedule {
     int lpr = 0;            // lanes per row (nvec >= 8); 0 = default
     int blocks_per_cu = 0;  // resident blocks per CU; 0 = as many as fit
     int stage_tables = 1;   // single-pass kernel: stage pattern and rank tables in LDS when they fit
+                            // (spaces wider than 32 bits: 1 = the two-level low-rank table in LDS,
+                            // 2 = only the pattern table, the full low table read through the caches)
     int nt_streams = 0;     // windowed kernel: non-temporal hints on partial sums, output and staged copies
     int sector_blocks = 0;  // sector bases: 1 = block-staged kernel (high-half blocks in LDS), 0 = the
                             // per-tile kernel (measured as fast or faster on every workload here)
@@ -163,6 +165,11 @@ struct hphi_basis {
     // half l = (a, b), b its low lr_b2 bits, has rank T1[a][class(l)] + T2[b]
     // among the low halves of its class (null if they would not fit in LDS)
     int lr_b2 = 0, lr_ncls = 0, lr_pairs = 0, lr_nsl = 0;
+    // their compact 16-bit form for the single-pass kernel (null if it does
+    // not apply): rank(l) = T1c[a][T2p[b] >> 10] + (T2p[b] & 1023)
+    int lr_n2 = 0;                // classes of a b2-bit part
+    uint16_t* d_t1c = nullptr;    // [2^(b_lo - lr_b2)][lr_n2]
+    uint16_t* d_t2p = nullptr;    // [2^lr_b2]
     uint32_t* d_t1 = nullptr;     // [2^(b_lo - lr_b2)][lr_ncls]
     uint16_t* d_t2 = nullptr;     // [2^lr_b2]
     size_t lr_bytes = 0;          // bytes of T1 and T2 as the kernel stages them

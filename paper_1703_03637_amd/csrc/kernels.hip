@@ -60,6 +60,13 @@ __device__ __forceinline__ int64_t find_high(const int64_t* __restrict__ h_tile,
     return lo;
 }
 
+// charge class of a low half: its popcount, or (fermions at fixed up and
+// down counts) n_even * (nsl + 1) + n_odd over its nsl sites
+__device__ __forceinline__ int low_class(uint32_t l, int cls_pairs, int nsl) {
+    if (!cls_pairs) return __popc(l);
+    return __popc(l & 0x55555555u) * (nsl + 1) + __popc(l & 0xAAAAAAAAu);
+}
+
 // largest k in [0, n) with h_row[k] <= row
 __device__ __forceinline__ int64_t find_high_row(const int64_t* __restrict__ h_row, int64_t n, int64_t row) {
     int64_t lo = 0, hi = n - 1;
@@ -333,6 +340,13 @@ struct HvArgs {
     const int* stop;
     double* partials;
     ExportArgs ex;       // element export (EXPORT instantiations only)
+    // two-level low-rank table (TAB 3), compact form: with l = (a, b), b its
+    // low b2 bits, rank(l) = T1c[a][class(b)] + (T2p[b] & 1023); class(b) is
+    // popcount(b), or for fermions at fixed up and down counts
+    // popcount(b & even) * w2 + popcount(b & odd)
+    const uint16_t* t1c; // [2^(b_lo - b2)][n2]
+    const uint16_t* t2p; // [2^b2]
+    int32_t b2, n2, cls_pairs, w2;
 };
 
 // the packed operator table seen through the constant address space
@@ -502,9 +516,13 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
 
     // pattern table and (sector) low rank table: staged in LDS, or global.
     // The high rank table is read with scalar loads: every row of a tile
-    // shares its high half, so the target's high half is uniform.
+    // shares its high half, so the target's high half is uniform.  TAB 3
+    // (spaces whose full low table is too large for LDS): the two-level
+    // low-rank table in LDS, 16-bit entries.
     const double* tab;
     const uint32_t* jlo = nullptr;
+    const uint16_t* lt1 = nullptr;
+    const uint16_t* lt2 = nullptr;
     typedef const __attribute__((address_space(4))) int64_t ConstI64;
     const ConstI64* jhi = (const ConstI64*)(bs.j_hi);
     if constexpr (TAB == 1) {
@@ -520,6 +538,14 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                 const int n_lo = 1 << bs.b_lo;
                 stage_to_lds(ll, bs.j_lo, size_t(n_lo) * 4);
                 jlo = ll;
+            } else if constexpr (TAB == 3) {
+                uint16_t* s1 = reinterpret_cast<uint16_t*>(lt + n_ops * 16);
+                const int n1 = (1 << (bs.b_lo - A.b2)) * A.n2;
+                uint16_t* s2 = s1 + (n1 + 7) / 8 * 8;
+                stage_to_lds(s1, A.t1c, (size_t(n1) * 2 + 3) / 4 * 4);
+                stage_to_lds(s2, A.t2p, (size_t(1) << A.b2) * 2);
+                lt1 = s1;
+                lt2 = s2;
             } else {
                 jlo = bs.j_lo;   // too large for LDS: read through the caches
             }
@@ -647,6 +673,17 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                         uint32_t part_lo = uint32_t(row - hrow);
                         if constexpr (TAB == 0) {
                             if (xm_lo) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
+                        } else if constexpr (TAB == 3) {
+                            if (xm_lo) {
+                                const uint32_t l = uint32_t(uint64_t(s) & bs.mask_lo) ^ uint32_t(xm_lo);
+                                // the two reads are independent: the class of b is
+                                // counted here rather than read from T2p
+                                const uint32_t b = l & ((1u << A.b2) - 1u);
+                                const uint32_t cb = A.cls_pairs
+                                    ? uint32_t(__popc(b & 0x55555555u)) * uint32_t(A.w2) + uint32_t(__popc(b & 0xAAAAAAAAu))
+                                    : uint32_t(__popc(b));
+                                part_lo = uint32_t(lt1[(l >> A.b2) * uint32_t(A.n2) + cb]) + (uint32_t(lt2[b]) & 1023u);
+                            }
                         } else {
                             const bool nz = CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0);
                             if (xm_lo && live && nz) part_lo = jlo[(uint64_t(s) & bs.mask_lo) ^ xm_lo];
@@ -742,7 +779,16 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
     }
     if constexpr (EXPORT) return;
 
-    __shared__ double sh[kWavesPerBlock][kNQ][64];
+    // block sums: TAB 3 reuses its dynamic LDS (at least this size) once
+    // every wavefront is done with the tables, the others a static array
+    double (*sh)[kNQ][64];
+    if constexpr (TAB == 3) {
+        __syncthreads();
+        sh = reinterpret_cast<double (*)[kNQ][64]>(lds_dyn);
+    } else {
+        __shared__ double sh_s[kWavesPerBlock][kNQ][64];
+        sh = sh_s;
+    }
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) sh[wave][k][lane] = wq[k];
     __syncthreads();
@@ -822,10 +868,6 @@ struct HvsArgs {
 
 constexpr int kBlockS = 512;   // threads of the block-staged sector kernel
 
-__device__ __forceinline__ int low_class(uint32_t l, int cls_pairs, int nsl) {
-    if (!cls_pairs) return __popc(l);
-    return __popc(l & 0x55555555u) * (nsl + 1) + __popc(l & 0xAAAAAAAAu);
-}
 
 // LDS row of a staged chunk -> registers (one lane holds a whole row)
 template <typename S, int NE>
@@ -2031,9 +2073,9 @@ static size_t hv_stage_bytes(const hphi_ham* H, bool sector) {
 }
 
 // resident blocks per CU once `lds` bytes of dynamic LDS are taken
-static int occupancy_with_lds(int occ, size_t lds) {
-    constexpr size_t kLdsPerCu = 160 * 1024, kStatic = 8 * 1024;
-    const int by_lds = int(kLdsPerCu / (lds + kStatic));
+static int occupancy_with_lds(int occ, size_t lds, size_t stat = 8 * 1024) {
+    constexpr size_t kLdsPerCu = 160 * 1024;
+    const int by_lds = int(kLdsPerCu / (lds + stat));
     return by_lds < occ ? (by_lds < 1 ? 1 : by_lds) : occ;
 }
 
@@ -2042,7 +2084,7 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     const hphi_ham* H = L.ham;
     static const int occ = occupancy_blocks(hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EX>);
     const int64_t tiles = EX ? L.ex->t1 - L.ex->t0 : H->basis->dev.n_tiles;
-    const int grid = make_grid(occupancy_with_lds(occ, lds), sc, tiles < 1 ? 1 : tiles);
+    const int grid = make_grid(occupancy_with_lds(occ, lds, TAB == 3 ? 0 : 8 * 1024), sc, tiles < 1 ? 1 : tiles);
     HvArgs A;
     A.bs = H->basis->dev;
     A.ops = H->d_ops;
@@ -2058,6 +2100,15 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     A.stop = L.stop;
     A.partials = H->d_partials;
     if constexpr (EX) A.ex = *L.ex;
+    if constexpr (TAB == 3) {
+        const hphi_basis* Bs = H->basis;
+        A.t1c = Bs->d_t1c;
+        A.t2p = Bs->d_t2p;
+        A.b2 = Bs->lr_b2;
+        A.n2 = Bs->lr_n2;
+        A.cls_pairs = Bs->lr_pairs;
+        A.w2 = Bs->lr_b2 / 2 + 1;
+    }
     hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EX><<<grid, kBlock, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
@@ -2079,6 +2130,17 @@ static int launch_hv_t(const HvLaunch& L, const Schedule& sc, hipStream_t st) {
         const size_t lds = hv_stage_bytes(L.ham, SECTOR);
         if (sc.stage_tables && lds <= kLdsStageBytes)
             return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 0, EX>(L, sc, lds, st);
+    }
+    if constexpr (SECTOR && W64) {
+        // the two-level low-rank table in LDS (16-bit entries) when it fits
+        const hphi_basis* Bs = L.ham->basis;
+        if (sc.stage_tables == 1 && Bs->d_t1c) {
+            const size_t n1 = (size_t(1) << (Bs->b_lo - Bs->lr_b2)) * size_t(Bs->lr_n2);
+            // at least the block-sum array, which this variant keeps in the same space
+            const size_t lds = std::max(ptab + (n1 + 7) / 8 * 16 + (size_t(1) << Bs->lr_b2) * 2,
+                                        size_t(kWavesPerBlock) * kNQ * 64 * sizeof(double));
+            if (lds <= kLdsStageBytes) return launch_hv_g<S, CPLX, CCOEF, SECTOR, B, LPR, W64, 3, EX>(L, sc, lds, st);
+        }
     }
     if constexpr (SECTOR) {
         if (sc.stage_tables && ptab <= kLdsStageBytes)

@@ -9,6 +9,7 @@
 // HPHI_TUNE_CACHE set, choices are appended to that file, keyed by a
 // signature of the device, the space and the packed operators, and are
 // reused by later processes without timing.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,13 +26,15 @@ int env_int(const char* name, int dflt) {
     return (e && *e) ? atoi(e) : dflt;
 }
 
-Schedule default_schedule(int nvec) {
+Schedule default_schedule(const hphi_basis* B, int nvec) {
     Schedule s;
     s.windowed = 1;
     s.window_kb = 2048;
     s.max_passes = 3;
     s.lpr = nvec >= 16 ? 4 : (nvec >= 8 ? 2 : 1);
-    s.blocks_per_cu = 0;
+    // sectors wider than 32 bits: 6 resident blocks per CU measured fastest
+    // (more waves in flight thrash the L2 on the 36-bit kagome sector)
+    s.blocks_per_cu = (B->dev.sector != 0 && B->nbits > 32) ? 6 : 0;
     s.nt_streams = nvec >= 8 ? 1 : 0;
     // overrides for experiments
     s.windowed = env_int("HPHI_WINDOWED", s.windowed);
@@ -40,7 +43,7 @@ Schedule default_schedule(int nvec) {
     const int l = env_int("HPHI_LPR", 0);
     if ((l == 1 || l == 2 || l == 4 || l == 8) && l <= nvec) s.lpr = l;
     s.blocks_per_cu = env_int("HPHI_BLOCKS_PER_CU", s.blocks_per_cu);
-    s.stage_tables = env_int("HPHI_STAGE_TABLES", s.stage_tables) ? 1 : 0;
+    s.stage_tables = std::min(2, std::max(0, env_int("HPHI_STAGE_TABLES", s.stage_tables)));
     s.nt_streams = env_int("HPHI_NT_STREAMS", s.nt_streams) ? 1 : 0;
     s.sector_blocks = env_int("HPHI_SECTOR_BLOCKS", s.sector_blocks);
     if (s.window_kb < 1) s.window_kb = 2048;
@@ -107,7 +110,7 @@ Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype) {
         for (const auto& t : H->tuned)
             if (t.nvec == nvec && t.dtype == dtype) return t.s;
     }
-    Schedule s = default_schedule(nvec);
+    Schedule s = default_schedule(H->basis, nvec);
     if (getenv("HPHI_TUNE_CACHE")) {
         Schedule c;
         if (cache_lookup(signature(H, nvec, dtype), c)) s = c;
@@ -139,7 +142,8 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
     std::vector<int> lprs = {1};
     if (nvec >= 8) lprs = {1, 2, 4, 8};
     else if (nvec >= 2) lprs = nvec >= 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2};
-    for (int bpc : {0, 4}) {
+    const bool wide_sector = B->dev.sector != 0 && B->nbits > 32;
+    for (int bpc : (wide_sector ? std::vector<int>{0, 4, 6} : std::vector<int>{0, 4})) {
         for (int lpr : lprs) {
             Schedule s;
             s.sector_blocks = 0;
@@ -150,6 +154,10 @@ extern "C" int hphi_hv_tune(const hphi_ham* ham, const void* v, void* u, int64_t
             s.max_passes = 1;
             for (int tables : {1, 0}) {
                 s.stage_tables = tables;
+                cands.push_back(s);
+            }
+            if (B->dev.sector != 0 && B->nbits > 32 && B->d_t1) {
+                s.stage_tables = 2;   // only the pattern table in LDS, not the two-level rank table
                 cands.push_back(s);
             }
             s.stage_tables = 1;

@@ -70,10 +70,14 @@ def _w64_case(name):
     return desc, terms, states
 
 
+@pytest.mark.parametrize("stage", [1, 2, 0])
 @pytest.mark.parametrize("name", list(W64_CASES))
-def test_w64_small_sectors_match_oracle(name):
-    """36-bit configurations: rank/unrank, element lists (bit-exact) and FP64 products (1e-12)."""
-    print(f"[gpu] w64 {name}", flush=True)
+def test_w64_small_sectors_match_oracle(monkeypatch, name, stage):
+    """36-bit configurations: rank/unrank, element lists (bit-exact) and FP64 products (1e-12), with
+    the low rank from the two-level table in LDS (stage 1), from the full table through the caches
+    (stage 2), and with every table in global memory (stage 0)."""
+    monkeypatch.setenv("HPHI_STAGE_TABLES", str(stage))
+    print(f"[gpu] w64 {name} stage={stage}", flush=True)
     desc, terms, states = _w64_case(name)
     basis = hp.hphi_basis_build(desc)
     assert basis.dim == len(states)
