@@ -747,7 +747,7 @@ def run_kagome36(args, hp, torch, np):
                       "residual": r["residual"],
                       "peak_memory_gb": torch.cuda.max_memory_allocated() / 1e9}
         print(f"[kagome36] {label}: {json.dumps(out[label])}", file=sys.stderr, flush=True)
-        del work, x_out, u
+        del work, x_out, u, r      # r holds the eigenvector (x_out) too
         torch.cuda.empty_cache()
         torch.cuda.reset_peak_memory_stats()
     f32, f64 = out["fp32"], out["fp64"]
