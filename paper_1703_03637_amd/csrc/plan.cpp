@@ -224,6 +224,13 @@ PassPlan* build_plan(const hphi_ham* H, int row_bytes, int window_kb, int max_pa
                 if ((k64[o].xm >> b) & 1u) m |= 1u << P->inv[size_t(p) * 64 + b];
             k64[o].lq = (k64[o].xm != 0 && m < 64u) ? m : ~0u;
         }
+    // within a pass, partners on chip first (ascending in-tile flip mask), then
+    // the gathers from memory: an operator group then mixes the two kinds at
+    // most once per pass, and a group of memory gathers never waits on the
+    // loads of an earlier in-tile read into the same registers
+    for (int p = 0; p < P->n_pass; ++p)
+        std::stable_sort(k64.begin() + P->kop_begin[p], k64.begin() + P->kop_begin[p + 1],
+                         [](const KOp<double>& a, const KOp<double>& b) { return a.lq < b.lq; });
     std::vector<KOp<double>> kq = k64;
     for (int p = 1; p < P->n_pass; ++p)
         for (int o = P->kop_begin[p]; o < P->kop_begin[p + 1]; ++o) {
