@@ -634,6 +634,7 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
             for (int o = 0; o < n_ops; o += 4) {
                 double crk[4], cik[4];
                 int64_t ik[4];
+                bool actk[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const ConstOp& op = ops[o + k];
@@ -651,9 +652,11 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                         dd = 0.0;
                     }
                     dsum += dd;
-                    if (smask != 0 && parity_masked<W64>(s, smask)) {
-                        cr = -cr;
-                        ci = -ci;
+                    if (smask != 0) {
+                        // the fermion sign: flip the sign bits of the element
+                        const int32_t sg = int32_t(parity_masked<W64>(s, smask) << 31);
+                        cr = __hiloint2double(__double2hiint(cr) ^ sg, __double2loint(cr));
+                        if constexpr (CCOEF) ci = __hiloint2double(__double2hiint(ci) ^ sg, __double2loint(ci));
                     }
                     int64_t idx;
                     bool live = valid;
@@ -692,8 +695,16 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                     } else {
                         idx = int64_t(s ^ ST(xmask));
                     }
-                    crk[k] = live ? cr : 0.0;
-                    cik[k] = live ? ci : 0.0;
+                    if constexpr (EXPORT) {
+                        crk[k] = live ? cr : 0.0;
+                        cik[k] = live ? ci : 0.0;
+                    } else {
+                        // a lane whose element is zero skips the gather and adds
+                        // zero in its place (the accumulation selects on actk)
+                        crk[k] = cr;
+                        cik[k] = ci;
+                        actk[k] = live && (CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0));
+                    }
                     ik[k] = idx;
                 }
                 if constexpr (SECTOR) {
@@ -716,12 +727,9 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                     }
                     continue;
                 }
-                bool actk[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
+                for (int k = 0; k < 4; ++k)
                     if (actk[k]) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
-                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL, true>(acc, g[k], actk[k], crk[k], cik[k]);
             }
