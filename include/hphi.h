@@ -223,15 +223,17 @@ int hphi_hv(const hphi_ham* ham, const void* v, void* u, int64_t nvec, int32_t d
  * multi-pass traversal with 1, 2 or 4 MB L2 windows and up to 3 passes,
  * gathering from v itself or from staged copies of v in each pass's row
  * order, or a single natural-order pass; lanes per row (nvec >= 2); resident blocks
- * per CU, table placement -- and pins the fastest for this (ham, nvec, dtype): later
+ * per CU, table placement -- and pins the fastest for this (ham, nvec, dtype) (the
+ * candidates within 5% of the fastest are timed again, best of 3 x 3 calls): later
  * hphi_hv / hphi_tpq_step / hphi_lanczos calls with that nvec and dtype use
  * it.  Results are bitwise reproducible for a fixed schedule; a different
  * schedule may change the last bits of the reductions.  sched_out (host,
  * may be NULL) receives 9 ints: windowed (0: single pass, 1: windowed,
  * 2: windowed with staged copies), window_kb, max_passes,
  * lanes_per_row, blocks_per_cu, stage_tables (single-pass kernel: 1 =
- * pattern and rank tables staged in LDS when they fit, 0 = read from
- * global memory), nt_streams (windowed kernel, nvec >= 8: 1 = partial
+ * pattern and rank tables staged in LDS when they fit -- on sectors wider
+ * than 32 bits the two-level low-rank table --, 2 = only the pattern table
+ * in LDS, 0 = read from global memory), nt_streams (windowed kernel, nvec >= 8: 1 = partial
  * sums, output and staged copies move with non-temporal hints so they do
  * not evict the gather window from L2), sector_blocks (sector bases: 1 = the
  * block-staged kernel that keeps each high-half block of rows in LDS, 0 =
