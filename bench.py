@@ -253,6 +253,9 @@ def run_headline(args, hp, torch, np):
     ms_b, st_b = run_tpq_steps(hp, ham, psi_b, args.steps, args.warmup, l, torch)
     ms_1, st_1 = run_tpq_steps(hp, ham, psi_1, args.steps, args.warmup, l, torch)
     ms_bg, _ = run_tpq_graph(hp, ham, psi_b, args.steps, args.warmup, l, torch)
+    # the same call over ten times as many steps: the graph instantiation amortized
+    long_steps = 10 * args.steps
+    ms_bg_long, _ = run_tpq_graph(hp, ham, psi_b, long_steps, 0, l, torch)
 
     # ---- dominant kernel alone: the batched product exactly as a step calls it (a, b, input scale,
     # reductions), HIP events on the stream it runs on; and one eager step per call for comparison
@@ -293,7 +296,8 @@ def run_headline(args, hp, torch, np):
                    "storage": "complex64", "reductions": "fp64",
                    "timed_call": "hphi_tpq_step, one call per step"},
         "graph_run": {"ms_per_step": ms_bg, "call": "hphi_tpq_run over the same K steps (graph instantiation "
-                                                      "and the first, eager step included)"},
+                                                      "and the first, eager step included)",
+                      "ms_per_step_long": ms_bg_long, "long_steps": long_steps},
         "hbm_gbps_step": alg_bytes / (ms_b * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(sched_b),
