@@ -630,8 +630,12 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
             double dsum = 0.0;
 
             // operators in groups of 4: decode all, issue every gather, then
-            // accumulate (FP64 coefficients and sums)
+            // accumulate (FP64 coefficients and sums). Wave priority rises with
+            // the phase (decode 1, gather issue 2, accumulation 0), so the SIMD's
+            // arbiter favours waves about to put loads in flight over waves that
+            // wait on theirs, and more gathers overlap.
             for (int o = 0; o < n_ops; o += 4) {
+                if constexpr (!EXPORT) __builtin_amdgcn_s_setprio(1);
                 double crk[4], cik[4];
                 int64_t ik[4];
                 bool actk[4];
@@ -727,9 +731,11 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                     }
                     continue;
                 }
+                __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (actk[k]) load_lane<S, NE, LPR>(v, ik[k], sub, g[k]);
+                __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL, true>(acc, g[k], actk[k], crk[k], cik[k]);
             }
@@ -1286,8 +1292,10 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
             for (int e = 0; e < NE; ++e) acc[e] = 0.0;
             double dsum = 0.0;
             // operators in groups of 4: decode all, issue every gather, then
-            // accumulate (FP64 coefficients and sums)
+            // accumulate (FP64 coefficients and sums), with the wave priority of
+            // the single-pass kernel's phases
             for (int o = 0; o < n_ops; o += 4) {
+                if constexpr (!EXPORT) __builtin_amdgcn_s_setprio(1);
                 double crk[4], cik[4];
                 uint32_t tk[4];
                 bool lk[4];   // partner on chip: in the LDS tile, or in this wavefront pass (uniform)
@@ -1345,6 +1353,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                     continue;
                 }
                 bool actk[4];
+                __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
@@ -1355,6 +1364,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                         load_lane_at<S, NE, LPR>(row_or_zero<S, NE, LPR>(v, int64_t(tk[k]), actk[k]), sub, g[k]);
                     }
                 }
+                __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) accumulate<S, CPLX, CCOEF, VPL>(acc, g[k], actk[k], crk[k], cik[k]);
             }
