@@ -282,6 +282,35 @@ __device__ __forceinline__ const char* row_or_zero(const S* v, int64_t idx, bool
                : reinterpret_cast<const char*>(kZeroRow);
 }
 
+// Byte offset in a wavefront's LDS tile of the lane's first chunk of row r
+// (the layout of tile_chunk: odd rows swap the two halves of the row); its
+// chunk j then sits at offset ^ (j * LPR * CB)
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ uint32_t tile_off(int r, uint32_t sub_cb) {
+    using Ly = LaneLayout<S, NE, LPR>;
+    constexpr int NCR = Ly::RB / Ly::CB;
+    uint32_t off = uint32_t(r) * uint32_t(Ly::RB) | sub_cb;
+    if constexpr (NCR >= 2) off ^= (uint32_t(r) & 1u) * uint32_t(Ly::RB / 2);
+    return off;
+}
+
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void tile_get_off(const char* tb, uint32_t off, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, tb + (off ^ uint32_t(j * LPR * Ly::CB)));
+}
+
+// the lane's share of a row, from the lane's own chunk address p
+template <typename S, int NE, int LPR>
+__device__ __forceinline__ void load_sub_at(const char* p, S (&out)[NE]) {
+    using Ly = LaneLayout<S, NE, LPR>;
+#pragma unroll
+    for (int j = 0; j < Ly::NCH; ++j)
+        copy_chunk<Ly::CB>(reinterpret_cast<char*>(out) + j * Ly::CB, p + j * LPR * Ly::CB);
+}
+
 // vector index of the lane's b-th vector (b < NE / NC)
 template <typename S, int NE, int LPR, int NC>
 __device__ __forceinline__ int lane_vec(int sub, int b) {
@@ -639,11 +668,28 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                 double crk[4], cik[4];
                 int64_t ik[4];
                 bool actk[4];
+                // the group's four records first, with one wait: scalar loads and
+                // LDS reads share a wait counter, so a record loaded between two
+                // pattern-table reads would also wait for the earlier read
+                uint32_t rbi[4], rbj[4];
+                uint64_t rxm[4], rsm[4], rcm[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    rbi[k] = ops[o + k].bi;
+                    rbj[k] = ops[o + k].bj;
+                    rxm[k] = ops[o + k].xmask;
+                    rsm[k] = ops[o + k].smask;
+                    rcm[k] = ops[o + k].cmask;
+                }
+                asm volatile("" : "+s"(rbi[0]), "+s"(rbi[1]), "+s"(rbi[2]), "+s"(rbi[3]), "+s"(rbj[0]), "+s"(rbj[1]),
+                                  "+s"(rbj[2]), "+s"(rbj[3]), "+s"(rxm[0]), "+s"(rxm[1]), "+s"(rxm[2]), "+s"(rxm[3]),
+                                  "+s"(rsm[0]), "+s"(rsm[1]), "+s"(rsm[2]), "+s"(rsm[3]),
+                                  "+s"(rcm[0]), "+s"(rcm[1]), "+s"(rcm[2]), "+s"(rcm[3]));
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const ConstOp& op = ops[o + k];
-                    const uint32_t bi = op.bi, bj = op.bj;
-                    const uint64_t xmask = op.xmask, smask = op.smask, cmask = op.cmask;
+                    const uint32_t bi = rbi[k], bj = rbj[k];
+                    const uint64_t xmask = rxm[k], smask = rsm[k], cmask = rcm[k];
                     const uint32_t pat = bit_at<W64>(s, bi) | (bit_at<W64>(s, bj) << 1);
                     const double* te = tab + ((o + k) * 4 + int(pat)) * 4;
                     double cr = te[0];
@@ -686,10 +732,10 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                                 // the two reads are independent: the class of b is
                                 // counted here rather than read from T2p
                                 const uint32_t b = l & ((1u << A.b2) - 1u);
-                                const uint32_t cb = A.cls_pairs
-                                    ? uint32_t(__popc(b & 0x55555555u)) * uint32_t(A.w2) + uint32_t(__popc(b & 0xAAAAAAAAu))
+                                const uint32_t cb = __builtin_amdgcn_readfirstlane(A.cls_pairs)
+                                    ? __umul24(uint32_t(__popc(b & 0x55555555u)), uint32_t(A.w2)) + uint32_t(__popc(b & 0xAAAAAAAAu))
                                     : uint32_t(__popc(b));
-                                part_lo = uint32_t(lt1[(l >> A.b2) * uint32_t(A.n2) + cb]) + (uint32_t(lt2[b]) & 1023u);
+                                part_lo = uint32_t(lt1[__umul24(l >> A.b2, uint32_t(A.n2)) + cb]) + (uint32_t(lt2[b]) & 1023u);
                             }
                         } else {
                             const bool nz = CCOEF ? (cr != 0.0 || ci != 0.0) : (cr != 0.0);
@@ -1234,6 +1280,10 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int e = 0; e < NE; ++e) g[k][e] = S(0);
+    // the lane's chunk of row 0 of v and of the zero row, and its chunk offset in a tile row
+    const char* const vsub = reinterpret_cast<const char*>(v) + sub * LaneLayout<S, NE, LPR>::CB;
+    const char* const zsub = reinterpret_cast<const char*>(kZeroRow) + sub * LaneLayout<S, NE, LPR>::CB;
+    const uint32_t sub_cb = uint32_t(sub * LaneLayout<S, NE, LPR>::CB);
 
     for (int64_t tile = t_begin + wl; tile < t_end; tile += waves_x) {
         // configuration bits of the tile index, and their next-pass index bits (uniform)
@@ -1298,6 +1348,7 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 if constexpr (!EXPORT) __builtin_amdgcn_s_setprio(1);
                 double crk[4], cik[4];
                 uint32_t tk[4];
+                uint32_t smk[4];   // sign masks (uniform)
                 bool lk[4];   // partner on chip: in the LDS tile, or in this wavefront pass (uniform)
                 int xa[4];
                 int opk[4];
@@ -1318,14 +1369,19 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                     } else {
                         dsum += te[1];
                     }
-                    if (sm != 0) {
-                        const bool neg = (__popc(s & sm) & 1) != 0;
-                        cr = neg ? -cr : cr;
-                        ci = neg ? -ci : ci;
-                    }
+                    smk[k] = sm;
                     crk[k] = cr;
                     cik[k] = ci;
                     tk[k] = base ^ xm;
+                }
+                if (__builtin_expect((smk[0] | smk[1] | smk[2] | smk[3]) != 0u, 0)) {
+                    // fermion signs: flip the sign bits where the parity is odd
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int32_t sg = int32_t((__popc(s & smk[k]) & 1u) << 31);
+                        crk[k] = __hiloint2double(__double2hiint(crk[k]) ^ sg, __double2loint(crk[k]));
+                        if constexpr (CCOEF) cik[k] = __hiloint2double(__double2hiint(cik[k]) ^ sg, __double2loint(cik[k]));
+                    }
                 }
                 if constexpr (EXPORT) {
 #pragma unroll
@@ -1358,10 +1414,10 @@ __global__ __launch_bounds__(kBlock) void hvw_kernel(HvwArgs A) {
                 for (int k = 0; k < 4; ++k) {
                     actk[k] = CCOEF ? (crk[k] != 0.0 || cik[k] != 0.0) : (crk[k] != 0.0);
                     if (lk[k]) {
-                        if constexpr (TL) tile_get<S, NE, LPR>(tb, actk[k] ? (r ^ int(xa[k])) : 64, sub, g[k]);
+                        if constexpr (TL) tile_get_off<S, NE, LPR>(tb, tile_off<S, NE, LPR>(actk[k] ? (r ^ int(xa[k])) : 64, sub_cb), g[k]);
                         else exchange_lane<S, NE>(vr, actk[k] ? xa[k] : (lane << 2), g[k]);
                     } else {
-                        load_lane_at<S, NE, LPR>(row_or_zero<S, NE, LPR>(v, int64_t(tk[k]), actk[k]), sub, g[k]);
+                        load_sub_at<S, NE, LPR>(actk[k] ? vsub + size_t(tk[k]) * LaneLayout<S, NE, LPR>::RB : zsub, g[k]);
                     }
                 }
                 __builtin_amdgcn_s_setprio(0);
