@@ -670,26 +670,31 @@ __device__ __forceinline__ void hv_body(const HvArgs& A, const int blk, const in
                 bool actk[4];
                 // the group's four records first, with one wait: scalar loads and
                 // LDS reads share a wait counter, so a record loaded between two
-                // pattern-table reads would also wait for the earlier read
+                // pattern-table reads would also wait for the earlier read (with one
+                // vector per lane; wider lanes hold too many scalar registers for it)
+                constexpr bool kPre = !EXPORT && VPL == 1;
                 uint32_t rbi[4], rbj[4];
                 uint64_t rxm[4], rsm[4], rcm[4];
+                if constexpr (kPre) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    rbi[k] = ops[o + k].bi;
-                    rbj[k] = ops[o + k].bj;
-                    rxm[k] = ops[o + k].xmask;
-                    rsm[k] = ops[o + k].smask;
-                    rcm[k] = ops[o + k].cmask;
+                    for (int k = 0; k < 4; ++k) {
+                        rbi[k] = ops[o + k].bi;
+                        rbj[k] = ops[o + k].bj;
+                        rxm[k] = ops[o + k].xmask;
+                        rsm[k] = ops[o + k].smask;
+                        rcm[k] = ops[o + k].cmask;
+                    }
+                    asm volatile("" : "+s"(rbi[0]), "+s"(rbi[1]), "+s"(rbi[2]), "+s"(rbi[3]), "+s"(rbj[0]), "+s"(rbj[1]),
+                                      "+s"(rbj[2]), "+s"(rbj[3]), "+s"(rxm[0]), "+s"(rxm[1]), "+s"(rxm[2]), "+s"(rxm[3]),
+                                      "+s"(rsm[0]), "+s"(rsm[1]), "+s"(rsm[2]), "+s"(rsm[3]),
+                                      "+s"(rcm[0]), "+s"(rcm[1]), "+s"(rcm[2]), "+s"(rcm[3]));
                 }
-                asm volatile("" : "+s"(rbi[0]), "+s"(rbi[1]), "+s"(rbi[2]), "+s"(rbi[3]), "+s"(rbj[0]), "+s"(rbj[1]),
-                                  "+s"(rbj[2]), "+s"(rbj[3]), "+s"(rxm[0]), "+s"(rxm[1]), "+s"(rxm[2]), "+s"(rxm[3]),
-                                  "+s"(rsm[0]), "+s"(rsm[1]), "+s"(rsm[2]), "+s"(rsm[3]),
-                                  "+s"(rcm[0]), "+s"(rcm[1]), "+s"(rcm[2]), "+s"(rcm[3]));
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const ConstOp& op = ops[o + k];
-                    const uint32_t bi = rbi[k], bj = rbj[k];
-                    const uint64_t xmask = rxm[k], smask = rsm[k], cmask = rcm[k];
+                    const uint32_t bi = kPre ? rbi[k] : op.bi, bj = kPre ? rbj[k] : op.bj;
+                    const uint64_t xmask = kPre ? rxm[k] : op.xmask, smask = kPre ? rsm[k] : op.smask,
+                                   cmask = kPre ? rcm[k] : op.cmask;
                     const uint32_t pat = bit_at<W64>(s, bi) | (bit_at<W64>(s, bj) << 1);
                     const double* te = tab + ((o + k) * 4 + int(pat)) * 4;
                     double cr = te[0];
