@@ -470,6 +470,37 @@ def test_tpq_trajectory_matches_oracle(dtype, tol):
         assert np.allclose(us[:, 2, bb], osv.tpq_beta(u_ref, ns, l), rtol=0, atol=100 * tol)
 
 
+@pytest.mark.parametrize("windowed,window_kb,passes", [(1, 1, 3), (1, 2, 2), (2, 1, 3), (1, 2048, 1)])
+@pytest.mark.parametrize("nvec,dtype,lpr", [(1, torch.complex128, 0), (4, torch.complex64, 1), (4, torch.complex64, 4),
+                                            (16, torch.complex64, 4), (8, torch.complex128, 2)])
+def test_hv_windowed_fermion_signs(monkeypatch, windowed, window_kb, passes, nvec, dtype, lpr):
+    """Fermion hopping on the full space of 6 orbitals (12 bits), Jordan-Wigner strings across the
+    windows (Sec. 3.3): products through the windowed kernel with one to three passes, plain or
+    staged, so that operator groups mix operators with and without sign masks, against the oracle's
+    sparse H."""
+    print(f"[gpu] windowed fermion signs windowed={windowed} kb={window_kb} passes={passes} nvec={nvec} "
+          f"{dtype} lpr={lpr}", flush=True)
+    for k, val in (("HPHI_WINDOWED", windowed), ("HPHI_L2_WINDOW_KB", window_kb), ("HPHI_PASSES", passes),
+                   ("HPHI_LPR", lpr)):
+        monkeypatch.setenv(k, str(val))
+    desc = BasisDesc("fermion", 6)
+    terms = L.random_fermion_terms(6, 20, 131, conserve_spin=False, real=False, n_dens=3, with_mu=True)
+    assert any(t.kind == "hop" for t in terms)
+    basis = hp.hphi_basis_build(desc)
+    ham = hp.hphi_ham_build(basis, terms)
+    st = ob.states(desc)
+    v = uniform_vectors(len(st), list(range(80, 80 + nvec)), True)
+    vd = _to_dev(v, dtype)
+    if nvec == 1:
+        vd = vd.reshape(-1)
+    vin = vd.cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    u = hp.hphi_hv(ham, vd).cpu().numpy().astype(np.complex128).reshape(len(st), nvec)
+    bound, H = _abs_bound(desc, terms, st, vin)
+    ref = H @ vin
+    tol = 1e-12 if dtype == torch.complex128 else len(terms) * 6e-8
+    assert np.all(np.abs(u - ref) <= tol * bound + 1e-300)
+
+
 @pytest.mark.parametrize("staged", [1, 2])
 @pytest.mark.parametrize("window_kb,nvec,passes", [(1, 1, 3), (2, 4, 2), (8, 16, 3), (8, 16, 2)])
 def test_hv_windowed_multipass(monkeypatch, window_kb, nvec, passes, staged):
