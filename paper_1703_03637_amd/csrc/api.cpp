@@ -430,14 +430,14 @@ int lz_iteration(const hphi_ham* H, int dtype, void* X, void* Y, bool first, LzD
     L.dtype = dtype;
     L.stop = stop;
     L.reduce_out = D.red;
+    // each reduction launch also takes the scalar step that reads its sums
+    L.lz_sc = D.sc;
+    L.lz_alpha = D.alpha;
+    L.lz_evec = acc ? D.evec : nullptr;
     int rc = launch_hv(L, st);
     if (rc) return rc;
-    rc = launch_lz_after_hv(D.sc, D.red, D.alpha, acc ? D.evec : nullptr, st);
-    if (rc) return rc;
-    rc = launch_lanczos_update(Y, X, H->basis->dim, dtype, &D.sc->c2, acc, &D.sc->ecoef, D.spart, grid, D.red, stop,
-                               H->d_flag, st);
-    if (rc) return rc;
-    return launch_lz_after_update(D.sc, D.red, D.beta, D.alpha, st);
+    return launch_lanczos_update_lz(Y, X, H->basis->dim, dtype, D.sc, acc, D.spart, grid, D.red, D.beta, D.alpha,
+                                    H->d_flag, st);
 }
 
 // Run the recurrence from v0 for n_max steps (pass 1 or the eigenvector pass).

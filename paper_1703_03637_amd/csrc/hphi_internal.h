@@ -234,6 +234,7 @@ struct ExportArgs {
 };
 
 // launch wrappers (kernels.hip)
+struct LzScalars;
 struct HvLaunch {
     const hphi_ham* ham;
     const void* v;
@@ -249,6 +250,11 @@ struct HvLaunch {
     const Schedule* sched;   // nullptr: the tuned or default schedule
     const ExportArgs* ex;    // non-null: element export instead of the product
     bool no_alloc;           // allocate nothing: only plans and staging buffers that exist already
+    // one Lanczos recurrence (nvec 1, stop == &lz_sc->stop): the launch that
+    // reduces the sums also takes the scalar step after the product
+    LzScalars* lz_sc;
+    double* lz_alpha;
+    const double* lz_evec;
 };
 Schedule schedule_for(const hphi_ham* ham, int nvec, int dtype);
 int launch_hv(const HvLaunch& L, hipStream_t st);
@@ -264,6 +270,11 @@ int launch_copy_norm(const void* src, void* dst, int64_t n, int dtype, double* p
 int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const double* c2,
                           void* acc, const double* ecoef, double* partials, int grid, double* red,
                           const int* stop, int32_t* flag, hipStream_t st);
+// the same update, with the reduction of |y|^2 and the scalar step after the
+// update (beta, stop test, next scales) in one launch
+int launch_lanczos_update_lz(void* y, const void* x, int64_t n, int dtype, LzScalars* sc, void* acc,
+                             double* partials, int grid, double* red, double* beta, const double* alpha,
+                             int32_t* flag, hipStream_t st);
 int launch_fill_zero(void* p, int64_t bytes, hipStream_t st);
 // w = a x + b y (FP64, n scalars; w may alias x or y); |w|^2 into *norm2 if non-null
 int launch_lincomb(double* w, const double* x, const double* y, int64_t n, double a, double b, double* partials,
@@ -358,9 +369,6 @@ int launch_lz_after_hv_multi(LzScalars* sc, const double* red, double* alpha, co
                              hipStream_t st);
 int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta, const double* alpha, int stride,
                                  int n, hipStream_t st);
-int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec,
-                       hipStream_t st);
-int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st);
 
 // dense-block plan for clusters of M bits (cma.cpp); an error code if the
 // space or the operators do not fit

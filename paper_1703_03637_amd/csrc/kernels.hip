@@ -2049,31 +2049,17 @@ __global__ void lz_init_kernel(LzScalars* sc, const double* red, double tol, int
     sc->breakdown = nn > 0.0 ? 0 : 1;
 }
 
-// per-problem scalar steps; thread p handles problem p (red: kNQ per
-// problem, alpha/beta/evec: `stride` per problem)
-__global__ void lz_after_hv_kernel(LzScalars* scs, const double* reds, double* alphas, const double* evecs,
-                                   int stride, int n) {
-    const int p = int(threadIdx.x);
-    if (p >= n) return;
-    LzScalars* sc = scs + p;
-    if (sc->stop) return;
-    const double* red = reds + kNQ * p;
-    double* alpha = alphas + size_t(stride) * p;
+// The scalar steps of one recurrence (the caller has checked sc->stop):
+// after the product, alpha_k and the update's coefficients; after the
+// update, beta_{k+1}, the stop test and the next step's scales
+__device__ void lz_after_hv_step(LzScalars* sc, const double* red, double* alpha, const double* evec) {
     const double a = red[1];          // Re<v_k|H v_k>, v_k = s_cur * X
     alpha[sc->k] = a;
     sc->c2 = -a * sc->s_cur;
-    sc->ecoef = evecs ? evecs[size_t(stride) * p + sc->k] * sc->s_cur : 0.0;
+    sc->ecoef = evec ? evec[sc->k] * sc->s_cur : 0.0;
 }
 
-__global__ void lz_after_update_kernel(LzScalars* scs, const double* reds, double* betas, const double* alphas,
-                                       int stride, int n) {
-    const int p = int(threadIdx.x);
-    if (p >= n) return;
-    LzScalars* sc = scs + p;
-    if (sc->stop) return;
-    const double* red = reds + kNQ * p;
-    double* beta = betas + size_t(stride) * p;
-    const double* alpha = alphas + size_t(stride) * p;
+__device__ void lz_after_update_step(LzScalars* sc, const double* red, double* beta, const double* alpha) {
     const int k = sc->k;
     const double b = sqrt(red[0]);
     beta[k] = b;
@@ -2092,9 +2078,86 @@ __global__ void lz_after_update_kernel(LzScalars* scs, const double* reds, doubl
     sc->k = k + 1;
 }
 
+// per-problem scalar steps; thread p handles problem p (red: kNQ per
+// problem, alpha/beta/evec: `stride` per problem)
+__global__ void lz_after_hv_kernel(LzScalars* scs, const double* reds, double* alphas, const double* evecs,
+                                   int stride, int n) {
+    const int p = int(threadIdx.x);
+    if (p >= n) return;
+    LzScalars* sc = scs + p;
+    if (sc->stop) return;
+    lz_after_hv_step(sc, reds + kNQ * p, alphas + size_t(stride) * p, evecs ? evecs + size_t(stride) * p : nullptr);
+}
+
+__global__ void lz_after_update_kernel(LzScalars* scs, const double* reds, double* betas, const double* alphas,
+                                       int stride, int n) {
+    const int p = int(threadIdx.x);
+    if (p >= n) return;
+    LzScalars* sc = scs + p;
+    if (sc->stop) return;
+    lz_after_update_step(sc, reds + kNQ * p, betas + size_t(stride) * p, alphas + size_t(stride) * p);
+}
+
+// One recurrence: the product's sums and the scalar step that reads them, in
+// one launch. The block reduces the kNQ quantities with the summation order
+// of reduce_partials_kernel (so the sums are bitwise the same), then thread 0
+// takes the step.
+__global__ __launch_bounds__(256) void reduce_lz_after_hv_kernel(const double* __restrict__ partials, int n_parts,
+                                                                 double* __restrict__ out, int32_t* flag,
+                                                                 LzScalars* sc, double* alpha, const double* evec) {
+    if (sc->stop) return;
+    const int t = int(threadIdx.x);
+    double s[kNQ];
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) s[q] = 0.0;
+    for (int g = t; g < n_parts; g += 256)
+#pragma unroll
+        for (int q = 0; q < kNQ; ++q) s[q] += partials[size_t(g) * kNQ + q];
+    __shared__ double sh[kNQ][256];
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) sh[q][t] = s[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int q = 0; q < kNQ; ++q) sh[q][t] += sh[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int q = 0; q < kNQ; ++q) {
+            out[q] = sh[q][0];
+            if (flag && !isfinite(sh[q][0])) atomicOr(flag, HPHI_NONFINITE_PRODUCT);
+        }
+        lz_after_hv_step(sc, out, alpha, evec);
+    }
+}
+
+// the update's |y|^2 and the scalar step that reads it, in one launch
+__global__ __launch_bounds__(256) void reduce_lz_after_update_kernel(const double* __restrict__ partials, int n_parts,
+                                                                     double* __restrict__ out, int32_t* flag,
+                                                                     LzScalars* sc, double* beta, const double* alpha) {
+    if (sc->stop) return;
+    reduce_body(partials, n_parts, 1, 0, out, flag, HPHI_NONFINITE_NORM);
+    if (threadIdx.x == 0) lz_after_update_step(sc, out, beta, alpha);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+
+// the product's sums (and, for one Lanczos recurrence, the scalar step that
+// reads them)
+static int launch_product_reduce(const hphi_ham* H, int n_parts, int B, const HvLaunch& L, hipStream_t st) {
+    if (L.lz_sc) {
+        if (B != 1) return set_error(HPHI_EINVAL, "Lanczos step fused with the reduction needs one vector");
+        reduce_lz_after_hv_kernel<<<1, 256, 0, st>>>(H->d_partials, n_parts, L.reduce_out, H->d_flag, L.lz_sc,
+                                                     L.lz_alpha, L.lz_evec);
+    } else {
+        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, n_parts, kNQ * B, L.reduce_out, L.stop,
+                                                      H->d_flag, HPHI_NONFINITE_PRODUCT);
+    }
+    return check_hip(hipGetLastError(), "reduce launch");
+}
 
 size_t dtype_size(int dtype) {
     switch (dtype) {
@@ -2191,11 +2254,7 @@ static int launch_hv_g(const HvLaunch& L, const Schedule& sc, size_t lds, hipStr
     hv_kernel<S, CPLX, CCOEF, SECTOR, B, LPR, W64, TAB, EX><<<grid, kBlock, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hv_kernel launch");
     if (rc) return rc;
-    if (!EX && L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop, H->d_flag,
-                                                      HPHI_NONFINITE_PRODUCT);
-        rc = check_hip(hipGetLastError(), "reduce launch");
-    }
+    if (!EX && L.reduce_out) rc = launch_product_reduce(H, grid, B, L, st);
     return rc;
 }
 
@@ -2322,11 +2381,7 @@ static int launch_hvs_t(const HvLaunch& L, int per_cu, hipStream_t st) {
     hvs_kernel<S, CPLX, CCOEF, B, W64><<<int(grid), kBlockS, lds, st>>>(A);
     int rc = check_hip(hipGetLastError(), "hvs_kernel launch");
     if (rc) return rc;
-    if (L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, int(grid), kNQ * B, L.reduce_out, L.stop,
-                                                      H->d_flag, HPHI_NONFINITE_PRODUCT);
-        rc = check_hip(hipGetLastError(), "reduce launch");
-    }
+    if (L.reduce_out) rc = launch_product_reduce(H, int(grid), B, L, st);
     return rc;
 }
 
@@ -2403,11 +2458,7 @@ static int launch_hvw_t(const HvLaunch& L, const PassPlan* P, const Schedule& sc
         int rc = check_hip(hipGetLastError(), "hvw_kernel launch");
         if (rc) return rc;
     }
-    if (!EX && L.reduce_out) {
-        reduce_partials_kernel<<<kNQ * B, 256, 0, st>>>(H->d_partials, grid, kNQ * B, L.reduce_out, L.stop, H->d_flag,
-                                                      HPHI_NONFINITE_PRODUCT);
-        return check_hip(hipGetLastError(), "reduce launch");
-    }
+    if (!EX && L.reduce_out) return launch_product_reduce(H, grid, B, L, st);
     return HPHI_OK;
 }
 
@@ -2668,6 +2719,24 @@ int launch_lanczos_update(void* y, const void* x, int64_t n, int dtype, const do
     return check_hip(hipGetLastError(), "reduce launch");
 }
 
+int launch_lanczos_update_lz(void* y, const void* x, int64_t n, int dtype, LzScalars* sc, void* acc,
+                             double* partials, int grid, double* red, double* beta, const double* alpha,
+                             int32_t* flag, hipStream_t st) {
+    const int64_t ns = n * (dtype_complex(dtype) ? 2 : 1);
+    if (grid <= 0) grid = stream_grid(ns);
+    const int* stop = &sc->stop;
+    if (dtype == HPHI_F64 || dtype == HPHI_C128)
+        lanczos_update_kernel<double><<<grid, 256, 0, st>>>((double*)y, (const double*)x, ns, &sc->c2, (double*)acc,
+                                                            &sc->ecoef, partials, stop);
+    else
+        lanczos_update_kernel<float><<<grid, 256, 0, st>>>((float*)y, (const float*)x, ns, &sc->c2, (double*)acc,
+                                                           &sc->ecoef, partials, stop);
+    int rc = check_hip(hipGetLastError(), "lanczos_update launch");
+    if (rc) return rc;
+    reduce_lz_after_update_kernel<<<1, 256, 0, st>>>(partials, grid, red, flag, sc, beta, alpha);
+    return check_hip(hipGetLastError(), "reduce launch");
+}
+
 int launch_lincomb(double* w, const double* x, const double* y, int64_t n, double a, double b, double* partials,
                    double* norm2, hipStream_t st) {
     const int grid = stream_grid(n);
@@ -2730,16 +2799,6 @@ int launch_tpq_obs_run(const double* red, TpqRunState* s, double* obs_log, int n
 int launch_lz_init(LzScalars* sc, const double* red, double tol, int n_max, hipStream_t st) {
     lz_init_kernel<<<1, 1, 0, st>>>(sc, red, tol, n_max);
     return check_hip(hipGetLastError(), "lz_init launch");
-}
-
-int launch_lz_after_hv(LzScalars* sc, const double* red, double* alpha, const double* evec, hipStream_t st) {
-    lz_after_hv_kernel<<<1, 64, 0, st>>>(sc, red, alpha, evec, 0, 1);
-    return check_hip(hipGetLastError(), "lz_after_hv launch");
-}
-
-int launch_lz_after_update(LzScalars* sc, const double* red, double* beta, const double* alpha, hipStream_t st) {
-    lz_after_update_kernel<<<1, 64, 0, st>>>(sc, red, beta, alpha, 0, 1);
-    return check_hip(hipGetLastError(), "lz_after_update launch");
 }
 
 // ---------------------------------------------------------------- batched
