@@ -569,12 +569,11 @@ int lzb_plans(const hphi_ham* const* H, int n, int dtype, void* const* A, void* 
     return HPHI_OK;
 }
 
-int lzb_iteration(const BatchPlans& P, int n, int parity, bool first, LzBatch& D, bool acc, int n_iter,
-                  hipStream_t st) {
-    int rc = hv_multi_launch(first ? P.hv_first : P.hv[parity], st);
-    if (!rc) rc = launch_lz_after_hv_multi(D.sc, D.red, D.alpha, acc ? D.evec : nullptr, n_iter, n, st);
-    if (!rc) rc = upd_multi_launch(P.upd[parity], st);
-    if (!rc) rc = launch_lz_after_update_multi(D.sc, D.red, D.beta, D.alpha, n_iter, n, st);
+int lzb_iteration(const BatchPlans& P, int parity, bool first, LzBatch& D, bool acc, int n_iter, hipStream_t st) {
+    // each reduction launch also takes the scalar steps that read its sums
+    const LzMulti lz{D.sc, D.alpha, D.beta, acc ? D.evec : nullptr, n_iter};
+    int rc = hv_multi_launch(first ? P.hv_first : P.hv[parity], &lz, st);
+    if (!rc) rc = upd_multi_launch(P.upd[parity], &lz, st);
     return rc;
 }
 
@@ -596,7 +595,7 @@ int lzb_run(const hphi_ham* const* H, int n, int dtype, const void* const* v0, v
     }
     BatchPlans P;
     int rc = lzb_plans(H, n, dtype, A, Bv, D, acc, P);
-    if (!rc) rc = lzb_iteration(P, n, 0, true, D, acc != nullptr, n_iter, st);
+    if (!rc) rc = lzb_iteration(P, 0, true, D, acc != nullptr, n_iter, st);
     int k = 1;
     if (!rc && use_graph && N >= 3) {
         hipStream_t cs;
@@ -610,8 +609,8 @@ int lzb_run(const hphi_ham* const* H, int n, int dtype, const void* const* v0, v
             hipGraphExec_t ge = nullptr;
             rc = check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
             if (!rc) {
-                int r1 = lzb_iteration(P, n, 1, false, D, acc != nullptr, n_iter, cs);
-                int r2 = r1 ? r1 : lzb_iteration(P, n, 0, false, D, acc != nullptr, n_iter, cs);
+                int r1 = lzb_iteration(P, 1, false, D, acc != nullptr, n_iter, cs);
+                int r2 = r1 ? r1 : lzb_iteration(P, 0, false, D, acc != nullptr, n_iter, cs);
                 hipError_t e = hipStreamEndCapture(cs, &g);
                 rc = r2 ? r2 : check_hip(e, "end capture");
             }
@@ -626,7 +625,7 @@ int lzb_run(const hphi_ham* const* H, int n, int dtype, const void* const* v0, v
             (void)hipEventDestroy(ev);
         }
     }
-    for (; !rc && k < N; ++k) rc = lzb_iteration(P, n, k & 1, false, D, acc != nullptr, n_iter, st);
+    for (; !rc && k < N; ++k) rc = lzb_iteration(P, k & 1, false, D, acc != nullptr, n_iter, st);
     // plans are read by kernels still in flight: release after the stream drains
     hipError_t e = hipStreamSynchronize(st);
     P.release();

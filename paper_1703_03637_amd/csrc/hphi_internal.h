@@ -352,7 +352,16 @@ struct MultiPlan {
 // Problems must agree on dtype, coefficient type, sector/full space and
 // configuration width (else HPHI_EINVAL); nvec must be 1.
 int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out);
-int hv_multi_launch(const MultiPlan& P, hipStream_t st);
+// the scalars of several recurrences (alpha/beta/evec: `stride` per problem);
+// with it, the launches that reduce the sums also take the scalar steps
+struct LzMulti {
+    LzScalars* sc;
+    double* alpha;
+    double* beta;
+    const double* evec;
+    int stride;
+};
+int hv_multi_launch(const MultiPlan& P, const LzMulti* lz, hipStream_t st);
 struct UpdPlan {
     int n = 0;
     int grid = 0;
@@ -364,11 +373,7 @@ struct UpdPlan {
 };
 // red_out[p]: device [1] receiving |y_p|^2
 int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int dtype, UpdPlan* out);
-int upd_multi_launch(const UpdPlan& P, hipStream_t st);
-int launch_lz_after_hv_multi(LzScalars* sc, const double* red, double* alpha, const double* evec, int stride, int n,
-                             hipStream_t st);
-int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta, const double* alpha, int stride,
-                                 int n, hipStream_t st);
+int upd_multi_launch(const UpdPlan& P, const LzMulti* lz, hipStream_t st);
 
 // dense-block plan for clusters of M bits (cma.cpp); an error code if the
 // space or the operators do not fit

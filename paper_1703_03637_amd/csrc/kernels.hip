@@ -2078,34 +2078,11 @@ __device__ void lz_after_update_step(LzScalars* sc, const double* red, double* b
     sc->k = k + 1;
 }
 
-// per-problem scalar steps; thread p handles problem p (red: kNQ per
-// problem, alpha/beta/evec: `stride` per problem)
-__global__ void lz_after_hv_kernel(LzScalars* scs, const double* reds, double* alphas, const double* evecs,
-                                   int stride, int n) {
-    const int p = int(threadIdx.x);
-    if (p >= n) return;
-    LzScalars* sc = scs + p;
-    if (sc->stop) return;
-    lz_after_hv_step(sc, reds + kNQ * p, alphas + size_t(stride) * p, evecs ? evecs + size_t(stride) * p : nullptr);
-}
-
-__global__ void lz_after_update_kernel(LzScalars* scs, const double* reds, double* betas, const double* alphas,
-                                       int stride, int n) {
-    const int p = int(threadIdx.x);
-    if (p >= n) return;
-    LzScalars* sc = scs + p;
-    if (sc->stop) return;
-    lz_after_update_step(sc, reds + kNQ * p, betas + size_t(stride) * p, alphas + size_t(stride) * p);
-}
-
-// One recurrence: the product's sums and the scalar step that reads them, in
-// one launch. The block reduces the kNQ quantities with the summation order
-// of reduce_partials_kernel (so the sums are bitwise the same), then thread 0
-// takes the step.
-__global__ __launch_bounds__(256) void reduce_lz_after_hv_kernel(const double* __restrict__ partials, int n_parts,
-                                                                 double* __restrict__ out, int32_t* flag,
-                                                                 LzScalars* sc, double* alpha, const double* evec) {
-    if (sc->stop) return;
+// The product's kNQ sums of one recurrence, with the summation order of
+// reduce_body (so the sums are bitwise those of reduce_partials_kernel), by
+// one block; thread 0 then takes the scalar step that reads them.
+__device__ __forceinline__ void reduce_nq_body(const double* __restrict__ partials, int n_parts,
+                                               double* __restrict__ out, int32_t* flag) {
     const int t = int(threadIdx.x);
     double s[kNQ];
 #pragma unroll
@@ -2123,13 +2100,21 @@ __global__ __launch_bounds__(256) void reduce_lz_after_hv_kernel(const double* _
             for (int q = 0; q < kNQ; ++q) sh[q][t] += sh[q][t + w];
         __syncthreads();
     }
-    if (t == 0) {
+    if (t == 0)
         for (int q = 0; q < kNQ; ++q) {
             out[q] = sh[q][0];
             if (flag && !isfinite(sh[q][0])) atomicOr(flag, HPHI_NONFINITE_PRODUCT);
         }
-        lz_after_hv_step(sc, out, alpha, evec);
-    }
+}
+
+// One recurrence: the product's sums and the scalar step that reads them, in
+// one launch (the step reads the sums thread 0 has just written)
+__global__ __launch_bounds__(256) void reduce_lz_after_hv_kernel(const double* __restrict__ partials, int n_parts,
+                                                                 double* __restrict__ out, int32_t* flag,
+                                                                 LzScalars* sc, double* alpha, const double* evec) {
+    if (sc->stop) return;
+    reduce_nq_body(partials, n_parts, out, flag);
+    if (threadIdx.x == 0) lz_after_hv_step(sc, out, alpha, evec);
 }
 
 // the update's |y|^2 and the scalar step that reads it, in one launch
@@ -2139,6 +2124,29 @@ __global__ __launch_bounds__(256) void reduce_lz_after_update_kernel(const doubl
     if (sc->stop) return;
     reduce_body(partials, n_parts, 1, 0, out, flag, HPHI_NONFINITE_NORM);
     if (threadIdx.x == 0) lz_after_update_step(sc, out, beta, alpha);
+}
+
+// the same for several recurrences: block p takes problem p (d[p]: its
+// partials and sums; alpha/beta/evec: `stride` per problem)
+__global__ __launch_bounds__(256) void reduce_lz_after_hv_multi_kernel(const RedDesc* __restrict__ d, LzScalars* scs,
+                                                                       double* alphas, const double* evecs, int stride) {
+    const int p = int(blockIdx.x);
+    LzScalars* sc = scs + p;
+    if (sc->stop) return;
+    reduce_nq_body(d[p].partials, d[p].n_parts, d[p].out, d[p].flag);
+    if (threadIdx.x == 0)
+        lz_after_hv_step(sc, d[p].out, alphas + size_t(stride) * p, evecs ? evecs + size_t(stride) * p : nullptr);
+}
+
+__global__ __launch_bounds__(256) void reduce_lz_after_update_multi_kernel(const RedDesc* __restrict__ d,
+                                                                           LzScalars* scs, double* betas,
+                                                                           const double* alphas, int stride) {
+    const int p = int(blockIdx.x);
+    LzScalars* sc = scs + p;
+    if (sc->stop) return;
+    reduce_body(d[p].partials, d[p].n_parts, 1, 0, d[p].out, d[p].flag, HPHI_NONFINITE_NORM);
+    if (threadIdx.x == 0)
+        lz_after_update_step(sc, d[p].out, betas + size_t(stride) * p, alphas + size_t(stride) * p);
 }
 
 }  // namespace
@@ -2807,10 +2815,7 @@ template <typename S, bool CPLX, bool CCOEF, bool SECTOR, bool W64, int TAB>
 static int hv_multi_go(const MultiPlan& P, hipStream_t st) {
     hv_multi_kernel<S, CPLX, CCOEF, SECTOR, 1, 1, W64, TAB><<<P.grid, kBlock, P.lds, st>>>(
         static_cast<const HvArgs*>(P.d_args), P.d_begin, P.n);
-    int rc = check_hip(hipGetLastError(), "hv_multi launch");
-    if (rc) return rc;
-    reduce_multi_kernel<<<P.n * kNQ, 256, 0, st>>>(P.d_red, kNQ);
-    return check_hip(hipGetLastError(), "reduce_multi launch");
+    return check_hip(hipGetLastError(), "hv_multi launch");
 }
 
 template <typename S, bool CPLX, bool CCOEF>
@@ -2826,7 +2831,7 @@ static int hv_multi_s(const MultiPlan& P, hipStream_t st) {
                   : hv_multi_go<S, CPLX, CCOEF, false, false, 0>(P, st);
 }
 
-int hv_multi_launch(const MultiPlan& P, hipStream_t st) {
+static int hv_multi_product(const MultiPlan& P, hipStream_t st) {
     switch (P.dtype) {
         case HPHI_F64: return hv_multi_s<double, false, false>(P, st);
         case HPHI_F32: return hv_multi_s<float, false, false>(P, st);
@@ -2834,6 +2839,16 @@ int hv_multi_launch(const MultiPlan& P, hipStream_t st) {
         case HPHI_C64: return P.cc ? hv_multi_s<float, true, true>(P, st) : hv_multi_s<float, true, false>(P, st);
     }
     return set_error(HPHI_EINVAL, "bad dtype %d", P.dtype);
+}
+
+int hv_multi_launch(const MultiPlan& P, const LzMulti* lz, hipStream_t st) {
+    int rc = hv_multi_product(P, st);
+    if (rc) return rc;
+    if (lz)
+        reduce_lz_after_hv_multi_kernel<<<P.n, 256, 0, st>>>(P.d_red, lz->sc, lz->alpha, lz->evec, lz->stride);
+    else
+        reduce_multi_kernel<<<P.n * kNQ, 256, 0, st>>>(P.d_red, kNQ);
+    return check_hip(hipGetLastError(), "reduce_multi launch");
 }
 
 int hv_multi_prepare(const HvLaunch* Ls, int n, MultiPlan* out) {
@@ -2996,29 +3011,18 @@ int upd_multi_prepare(const UpdDesc* descs, double* const* red_out, int n, int d
     return HPHI_OK;
 }
 
-int upd_multi_launch(const UpdPlan& P, hipStream_t st) {
+int upd_multi_launch(const UpdPlan& P, const LzMulti* lz, hipStream_t st) {
     if (P.fp64)
         lanczos_update_multi_kernel<double><<<P.grid, 256, 0, st>>>(P.d_desc, P.d_begin, P.n);
     else
         lanczos_update_multi_kernel<float><<<P.grid, 256, 0, st>>>(P.d_desc, P.d_begin, P.n);
     int rc = check_hip(hipGetLastError(), "update_multi launch");
     if (rc) return rc;
-    reduce_multi_kernel<<<P.n, 256, 0, st>>>(P.d_red, 1);
+    if (lz)
+        reduce_lz_after_update_multi_kernel<<<P.n, 256, 0, st>>>(P.d_red, lz->sc, lz->beta, lz->alpha, lz->stride);
+    else
+        reduce_multi_kernel<<<P.n, 256, 0, st>>>(P.d_red, 1);
     return check_hip(hipGetLastError(), "reduce_multi launch");
-}
-
-int launch_lz_after_hv_multi(LzScalars* sc, const double* red, double* alpha, const double* evec, int stride, int n,
-                             hipStream_t st) {
-    const int threads = (n + 63) / 64 * 64;
-    lz_after_hv_kernel<<<1, threads, 0, st>>>(sc, red, alpha, evec, stride, n);
-    return check_hip(hipGetLastError(), "lz_after_hv launch");
-}
-
-int launch_lz_after_update_multi(LzScalars* sc, const double* red, double* beta, const double* alpha, int stride,
-                                 int n, hipStream_t st) {
-    const int threads = (n + 63) / 64 * 64;
-    lz_after_update_kernel<<<1, threads, 0, st>>>(sc, red, beta, alpha, stride, n);
-    return check_hip(hipGetLastError(), "lz_after_update launch");
 }
 
 }  // namespace hphi
