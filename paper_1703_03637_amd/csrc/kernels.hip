@@ -2078,9 +2078,9 @@ __device__ void lz_after_update_step(LzScalars* sc, const double* red, double* b
     sc->k = k + 1;
 }
 
-// The product's kNQ sums of one recurrence, with the summation order of
-// reduce_body (so the sums are bitwise those of reduce_partials_kernel), by
-// one block; thread 0 then takes the scalar step that reads them.
+// The product's kNQ sums of one recurrence, reduced by one block with the
+// summation order of reduce_body (so they are bitwise those of
+// reduce_partials_kernel); thread 0 writes them and the flag.
 __device__ __forceinline__ void reduce_nq_body(const double* __restrict__ partials, int n_parts,
                                                double* __restrict__ out, int32_t* flag) {
     const int t = int(threadIdx.x);
